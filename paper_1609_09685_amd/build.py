@@ -1,0 +1,60 @@
+"""Builds the package's native libraries in-tree.
+
+* ``libqsgs.so``  - host C++ (OpenMP) mask generator, built with g++.
+* ``liblbm.so``   - the HIP solver library for gfx950 behind the C ABI in
+  ``include/lbm.h``, built with hipcc.
+
+Run ``python -m paper_1609_09685_amd.build`` (or ``__graft_entry__.build()``).
+"""
+import os
+import subprocess
+import sys
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+CSRC = os.path.join(PKG, "csrc")
+INCLUDE = os.path.join(ROOT, "include")
+QSGS_LIB = os.path.join(PKG, "libqsgs.so")
+LBM_LIB = os.path.join(PKG, "liblbm.so")
+ARCH = "gfx950"
+
+# Sources of liblbm.so, compiled together as one translation unit list.
+LBM_SOURCES = ["lbm_kernels.hip", "lbm_api.hip"]
+
+HIPCC_FLAGS = [
+    f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument",
+    # Packed FP32 instructions are kept out of every kernel.
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-munsafe-fp-atomics",
+]
+
+
+def _run(cmd, verbose):
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+
+
+def build_qsgs(verbose=False):
+    _run(["g++", "-O2", "-std=c++17", "-fopenmp", "-fPIC", "-shared", "-Wall",
+          "-o", QSGS_LIB + ".tmp", os.path.join(CSRC, "qsgs.cpp")], verbose)
+    os.replace(QSGS_LIB + ".tmp", QSGS_LIB)
+    return QSGS_LIB
+
+
+def build_lbm(verbose=False):
+    srcs = [os.path.join(CSRC, s) for s in LBM_SOURCES]
+    _run(["hipcc", *HIPCC_FLAGS, f"-I{INCLUDE}", f"-I{CSRC}", "-o", LBM_LIB + ".tmp", *srcs],
+         verbose)
+    os.replace(LBM_LIB + ".tmp", LBM_LIB)
+    return LBM_LIB
+
+
+def build_all(verbose=False):
+    build_qsgs(verbose)
+    build_lbm(verbose)
+
+
+if __name__ == "__main__":
+    build_all(verbose="-q" not in sys.argv)
