@@ -1,0 +1,143 @@
+"""Throughput benchmark of the lattice Boltzmann step on one MI355X.
+
+Default workload: D3Q19 BGK, FP32 deviation storage, 512^3 QSGS porous mask
+(porosity 0.6, seed 0), tau = 0.6, density drop 1e-4 along x, symmetric y/z
+planes.  One step = one launch of the fused stream-collide kernel over the
+whole lattice.  Prints one JSON line with MLUPS (all nodes), the roofline of
+the step kernel against HBM bandwidth, and the CPU checker's throughput on a
+bounded sample of the same workload.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
+METRIC = "MLUPS + % HBM roofline (D3Q19 FP32); time-to-converged k, warm vs plain"
+
+WORKLOADS = {
+    # name: (lattice, shape (nz, ny, nx), porosity, tau, rho_in, rho_out, precision)
+    "d3q19_512_fp32": (19, (512, 512, 512), 0.6, 0.6, 1.00005, 0.99995, "fp32"),
+    "d3q19_256_fp32": (19, (256, 256, 256), 0.6, 0.6, 1.00005, 0.99995, "fp32"),
+    "d2q9_400x200_fp32": (9, (1, 200, 400), 0.74, 0.8, 1.0005, 0.9995, "fp32"),
+    "d2q9_400x200_fp64": (9, (1, 200, 400), 0.74, 0.8, 1.0005, 0.9995, "fp64"),
+    "d2q9_100x50_fp64": (9, (1, 50, 100), 0.74, 0.8, 1.0005, 0.9995, "fp64"),
+}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def make_mask(Q, shape, porosity, seed=0):
+    from paper_1609_09685_amd.qsgs import qsgs_2d, qsgs_3d
+    nz, ny, nx = shape
+    if Q == 9:
+        return qsgs_2d(nx, ny, porosity, seed)
+    return qsgs_3d(nx, ny, nz, porosity, seed)
+
+
+def cpu_baseline(Q, mask, tau, rho_in, rho_out, budget_s=12.0):
+    """The CPU checker, as it stands, on a bounded sub-box of the workload."""
+    import oracle
+    if Q == 19:
+        sub = np.ascontiguousarray(mask[:256, :256, :256])
+    else:
+        sub = mask
+    o = oracle.Oracle(Q, sub, tau, rho_in, rho_out)
+    o.step(1)
+    steps, t0 = 0, time.perf_counter()
+    while True:
+        o.step(1)
+        steps += 1
+        dt = time.perf_counter() - t0
+        if dt >= budget_s or steps >= 10000:
+            break
+    n = sub.size
+    shape = "x".join(str(s) for s in (sub.shape[::-1] if sub.ndim == 3 else sub.shape[::-1]))
+    return {"value": n * steps / dt / 1e6, "unit": "MLUPS", "cores": oracle.threads(),
+            "kind": "oracle",
+            "sample": f"{steps} FP64 steps on the {shape} corner sub-box of the same mask "
+                      f"({dt:.1f} s wall)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="d3q19_512_fp32", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU runs are not "
+                                   "part of this build", "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    from paper_1609_09685_amd import lbm
+
+    Q, shape, phi, tau, rin, rout, prec = WORKLOADS[args.workload]
+    t0 = time.time()
+    mask = make_mask(Q, shape, phi)
+    log(f"mask {shape} porosity {1 - mask.mean():.4f} in {time.time() - t0:.1f} s")
+    torch.cuda.set_device(0)
+    s = lbm.Solver(mask, tau, rin, rout, precision=prec, lattice=Q)
+    N = int(mask.size)
+    n_fluid = int((mask == 0).sum())
+    esize = 8 if prec == "fp64" else 4
+    s.step(args.warmup)
+    torch.cuda.synchronize()
+    log(f"warmup {args.warmup} steps done")
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    s.step(args.steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    ms_step = ms / args.steps
+    k = s.permeability()
+    log(f"timed {args.steps} steps: {ms_step:.4f} ms/step, k after {s.steps} steps = {k:.6e}")
+    mlups = N * args.steps / (ms / 1e3) / 1e6
+    alg_bytes = n_fluid * 2 * Q * esize + N * 1
+    achieved = alg_bytes / (ms_step / 1e3) / 1e9
+    out = {
+        "metric": METRIC,
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if prec == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"D{'3Q19' if Q == 19 else '2Q9'} BGK {prec} deviation storage, "
+                               f"{'x'.join(map(str, shape[::-1]))} QSGS mask porosity {phi}, "
+                               f"tau {tau}, rho {rin}/{rout}, pressure x, symmetric y/z",
+                   "name": args.workload, "nodes": N, "fluid_nodes": n_fluid,
+                   "mflups": round(n_fluid * args.steps / (ms / 1e3) / 1e6, 1)},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "k_step", "algorithmic_bytes_per_launch": alg_bytes},
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline ...")
+        out["cpu_baseline"] = cpu_baseline(Q, mask, tau, rin, rout)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

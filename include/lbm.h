@@ -1,0 +1,167 @@
+/*
+ * lbm.h - C ABI of the MI355X lattice Boltzmann permeability solver.
+ *
+ * The solver computes the Darcy permeability of a voxelised porous medium as
+ * in Li, Ho, Wu & Zhang, "Lattice Boltzmann modelling of intrinsic
+ * permeability": single-relaxation-time (BGK) lattice Boltzmann with the
+ * normalised relaxation time tau (viscosity nu = (tau - 1/2)/3 in lattice
+ * units, Eq. 1), the D2Q9 and D3Q19 lattices, pressure-driven flow along x
+ * with density imposed at the inlet and outlet and symmetric side planes
+ * (Fig. 1 and the first paragraph of the Results), iterated to steady Stokes
+ * flow; the permeability follows from Darcy's law and the mass flow rate
+ * (same paragraph; Eq. 2 with the body force replaced by the pressure
+ * gradient), and Kn = sqrt(pi/6)(tau - 1/2)/Nx (discussion of Fig. 2).
+ *
+ * Boundary rules (the paper names them without giving a scheme):
+ *   solid voxels   halfway bounce-back;
+ *   y / z faces    specular mirror half a spacing outside the last node row;
+ *   x faces        ghost planes at x = -1 and x = nx carrying rho_in / rho_out
+ *                  by non-equilibrium extrapolation from the edge node
+ *                  (Guo, Zheng & Shi 2002); a ghost copies the solidity of the
+ *                  edge node it extrapolates from.
+ * Lengths are in lattice units; the permeability is in dx^2 with the pressure
+ * gradient taken between the ghost planes: k = nu Q L / (A c_s^2 (rho_in -
+ * rho_out)), L = nx + 1, A = ny * nz, c_s^2 = 1/3, and Q the mass flow rate,
+ * i.e. the x-momentum summed over the fluid nodes divided by nx.
+ *
+ * Conventions for every entry point:
+ *   - All device buffers are allocated and owned by the caller; the library
+ *     never allocates or frees device memory through these entry points.  The
+ *     buffers must stay alive, unmoved, until lbm_destroy.
+ *   - Work is enqueued on the caller's HIP stream (lbm_buffers.stream; NULL =
+ *     the legacy default stream).  Entry points that return values computed on
+ *     the device synchronise that stream only.
+ *   - Every function returns an lbm_status; on failure a message is available
+ *     from lbm_last_error() (per thread, valid until the next call on that
+ *     thread).  Arguments are validated before any HIP call; an invalid
+ *     argument leaves the context unchanged.  A fault inside a kernel shows up
+ *     as LBM_EHIP at the next call that checks the stream.
+ *   - One context may be driven by one host thread at a time; distinct
+ *     contexts are independent.
+ *
+ * Storage: populations are kept as deviations from the rest state,
+ * g_i = f_i - w_i rho0, population-major ("SoA"): g[i][z][y][x] with the x
+ * pitch padded to a multiple of 128 bytes, so that the tiny Stokes-regime
+ * pressure differences survive FP32 rounding.  The solid mask is uint8,
+ * [nz][ny][nx] with x fastest, 1 = solid, 0 = fluid.
+ */
+#ifndef LBM_H_
+#define LBM_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LBM_OK = 0,
+  LBM_EINVAL = -1,      /* invalid argument (see lbm_last_error)              */
+  LBM_EHIP = -2,        /* a HIP runtime call or kernel launch failed           */
+  LBM_ENOMEM = -3,      /* a caller buffer is smaller than lbm_query_sizes says */
+  LBM_ENONFINITE = -4,  /* the flux became NaN or infinite                      */
+  LBM_ENOTCONV = -5,    /* max_steps reached before the residual tolerance      */
+  LBM_ENOFLOW = -6,     /* zero mass flow rate: the medium does not percolate   */
+  LBM_ESTATE = -7       /* call not valid in the context's current state        */
+} lbm_status;
+
+enum { LBM_D2Q9 = 9, LBM_D3Q19 = 19 };
+enum { LBM_FP64 = 0, LBM_FP32 = 1 };          /* storage and in-kernel arithmetic */
+enum { LBM_START_UNIFORM = 0, LBM_START_LINEAR = 1 };
+
+typedef struct lbm_ctx lbm_ctx;               /* opaque; host metadata only */
+
+typedef struct {
+  int32_t lattice;      /* LBM_D2Q9 or LBM_D3Q19                                  */
+  int32_t nx, ny, nz;   /* lattice nodes; nz must be 1 for D2Q9; each >= 1, nx >= 2 */
+  int32_t precision;    /* LBM_FP64 or LBM_FP32                                    */
+  int32_t check_every;  /* K: steps between two convergence checks (>= 1)          */
+  double rho0;          /* reference density of the deviation storage (> 0)        */
+} lbm_geom;
+
+typedef struct {
+  void *f[2];           /* two population buffers, f_bytes each (ping-pong)        */
+  const void *mask;     /* device uint8 [nz][ny][nx], 1 = solid; read at init only */
+  void *work;           /* device scratch of work_bytes: link masks, boundary-plane
+                           moments, reduction partials                             */
+  void *stream;         /* hipStream_t the context enqueues on                     */
+} lbm_buffers;
+
+/* Bytes the caller must allocate for a geometry.  Fails with LBM_EINVAL on an
+ * invalid geometry. */
+lbm_status lbm_query_sizes(const lbm_geom *geom, size_t *f_bytes, size_t *work_bytes);
+
+/* Creates a context and starts from rest with uniform density
+ * (rho_in + rho_out)/2 (zero-velocity start).  Requires tau > 1/2 (positive
+ * viscosity, Eq. 1), rho_in > 0, rho_out > 0, non-NULL buffers.  Enqueues the
+ * set-up kernels; does not synchronise. */
+lbm_status lbm_init(lbm_ctx **out, const lbm_geom *geom, const lbm_buffers *bufs,
+                    double tau, double rho_in, double rho_out);
+
+/* Restarts from rest: LBM_START_UNIFORM (rho = (rho_in + rho_out)/2) or
+ * LBM_START_LINEAR (rho linear in x between the ghost planes,
+ * rho(x) = rho_in + (rho_out - rho_in)(x + 1)/(nx + 1)).  Resets the step count. */
+lbm_status lbm_reset(lbm_ctx *ctx, int32_t start);
+
+/* Restarts from given macroscopic fields: every fluid node gets the
+ * equilibrium populations of (rho, u).  rho: device float32 [nz][ny][nx];
+ * u: device float32 [D][nz][ny][nx] (D = 2 for D2Q9, 3 for D3Q19).  Values at
+ * solid nodes are ignored.  Resets the step count. */
+lbm_status lbm_set_macro(lbm_ctx *ctx, const float *rho, const float *u);
+
+/* Enqueues n >= 0 time steps (stream + collide). */
+lbm_status lbm_step(lbm_ctx *ctx, int64_t n);
+
+/* Mass flow rate Q of the current state (FP64 reduction, deterministic). */
+lbm_status lbm_flux(lbm_ctx *ctx, double *q_out);
+
+/* Darcy permeability of the current state in lattice units (dx^2).
+ * LBM_ENOFLOW (k_out = 0) if the flux is exactly zero. */
+lbm_status lbm_permeability(lbm_ctx *ctx, double *k_out);
+
+/* Steps until the relative change of the flux over one check window,
+ * |Q_t - Q_{t-K}| / |Q_t|, is below tol, checking every K = check_every steps
+ * (the first check compares with the flux of the starting state), or until
+ * the total step count would exceed max_steps.  steps_out: total steps of the
+ * context; resid_out: the last residual.  LBM_ENOTCONV if tol was not reached,
+ * LBM_ENONFINITE if the flux is NaN or infinite. */
+lbm_status lbm_run_to_steady(lbm_ctx *ctx, double tol, int64_t max_steps,
+                             int64_t *steps_out, double *resid_out);
+
+/* Macroscopic fields of the current state into caller device buffers:
+ * rho [nz][ny][nx], u [D][nz][ny][nx]; dtype 0 = float32, 1 = float64.
+ * Solid nodes get rho = rho0 and u = 0. */
+lbm_status lbm_get_macro(lbm_ctx *ctx, void *rho, void *u, int32_t dtype);
+
+/* Checkpoint / restore: copies the current population buffer (f_bytes, the
+ * library's internal layout and direction order) to / from device memory.
+ * lbm_set_populations keeps the step count. */
+lbm_status lbm_get_populations(lbm_ctx *ctx, void *dst);
+lbm_status lbm_set_populations(lbm_ctx *ctx, const void *src);
+
+/* Direction table of the internal order: c[3*Q] (x,y,z per direction) and
+ * w[Q].  Q = 9 or 19. */
+lbm_status lbm_lattice(int32_t lattice, int32_t *c, double *w);
+
+/* Steps taken since the last start. */
+lbm_status lbm_steps(const lbm_ctx *ctx, int64_t *steps_out);
+
+/* Kn = sqrt(pi/6)(tau - 1/2)/nx (discussion of Fig. 2). */
+double lbm_knudsen(double tau, int32_t nx);
+
+/* Releases the host-side context.  Does not touch caller buffers.  NULL is
+ * accepted. */
+lbm_status lbm_destroy(lbm_ctx *ctx);
+
+/* Message of the last failure on the calling thread ("" if none). */
+const char *lbm_last_error(void);
+
+/* Version of the library, e.g. "1.0.0". */
+const char *lbm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H_ */

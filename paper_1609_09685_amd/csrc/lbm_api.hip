@@ -1,0 +1,488 @@
+// Host side of the C ABI declared in include/lbm.h.
+//
+// A context holds host metadata only: the geometry, the physical parameters,
+// the caller's buffers and stream, the ping-pong parity and the step count.
+// Device memory is the caller's; the work buffer is carved here into
+//   links    uint32 [nz][ny][xp]             per-node link words
+//   bplane   T [2 parities][2 sides][D+1][nz][ny]   edge-node moments
+//   partial  double [step blocks]             flux partials
+//   scalars  double [8]                       reduced flux, ...
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+
+#include "kernels.h"
+#include "lbm.h"
+
+using namespace lbm;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+lbm_status fail(lbm_status s, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof g_err, fmt, ap);
+  va_end(ap);
+  return s;
+}
+
+lbm_status ok() {
+  g_err[0] = 0;
+  return LBM_OK;
+}
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail(LBM_EHIP, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__,   \
+                  __LINE__);                                                            \
+  } while (0)
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct Layout {
+  int Q, D;
+  size_t esize;          // bytes per population value
+  int xp;                // padded x pitch (elements)
+  uint64_t ps;           // elements per population array
+  size_t f_bytes;
+  int tiles_x, tiles_y, blocks;
+  size_t off_links, off_bplane, off_partial, off_scalar, work_bytes;
+  size_t bplane_one;     // elements of one parity of the boundary-plane array
+};
+
+lbm_status validate_geom(const lbm_geom* g) {
+  if (!g) return fail(LBM_EINVAL, "geom is NULL");
+  if (g->lattice != LBM_D2Q9 && g->lattice != LBM_D3Q19)
+    return fail(LBM_EINVAL, "lattice must be 9 (D2Q9) or 19 (D3Q19), got %d", g->lattice);
+  if (g->precision != LBM_FP64 && g->precision != LBM_FP32)
+    return fail(LBM_EINVAL, "precision must be LBM_FP64 or LBM_FP32, got %d", g->precision);
+  if (g->nx < 2 || g->ny < 1 || g->nz < 1)
+    return fail(LBM_EINVAL, "need nx >= 2, ny >= 1, nz >= 1 (got %d x %d x %d)", g->nx, g->ny, g->nz);
+  if (g->lattice == LBM_D2Q9 && g->nz != 1) return fail(LBM_EINVAL, "D2Q9 needs nz == 1");
+  if (g->check_every < 1) return fail(LBM_EINVAL, "check_every must be >= 1");
+  if (!(g->rho0 > 0.0) || !isfinite(g->rho0)) return fail(LBM_EINVAL, "rho0 must be > 0");
+  return LBM_OK;
+}
+
+lbm_status make_layout(const lbm_geom* g, Layout* L) {
+  lbm_status s = validate_geom(g);
+  if (s != LBM_OK) return s;
+  L->Q = g->lattice;
+  L->D = g->lattice == LBM_D2Q9 ? 2 : 3;
+  L->esize = g->precision == LBM_FP64 ? 8 : 4;
+  const int per_line = (int)(128 / L->esize);
+  L->xp = (int)align_up((size_t)g->nx, (size_t)per_line);
+  const uint64_t n_pad = (uint64_t)g->nz * g->ny * L->xp;
+  if (n_pad * L->esize >= (1ull << 32) || n_pad * 4 >= (1ull << 32))
+    return fail(LBM_EINVAL, "domain too large: %llu padded nodes exceed 32-bit byte offsets",
+                (unsigned long long)n_pad);
+  L->ps = n_pad;
+  L->f_bytes = (size_t)L->Q * n_pad * L->esize;
+  L->tiles_x = (g->nx + kTileX - 1) / kTileX;
+  L->tiles_y = (g->ny + kTileY - 1) / kTileY;
+  const uint64_t blocks = (uint64_t)L->tiles_x * L->tiles_y * g->nz;
+  if (blocks >= (1ull << 31)) return fail(LBM_EINVAL, "too many blocks");
+  L->blocks = (int)blocks;
+  L->bplane_one = (size_t)2 * (L->D + 1) * g->nz * g->ny;
+  size_t off = 0;
+  L->off_links = off;
+  off = align_up(off + n_pad * 4, 256);
+  L->off_bplane = off;
+  off = align_up(off + 2 * L->bplane_one * L->esize, 256);
+  L->off_partial = off;
+  off = align_up(off + (size_t)L->blocks * 8, 256);
+  L->off_scalar = off;
+  off = align_up(off + 64, 256);
+  L->work_bytes = off;
+  return LBM_OK;
+}
+
+}  // namespace
+
+struct lbm_ctx {
+  lbm_geom g;
+  Layout L;
+  void* f[2];
+  const uint8_t* mask;
+  uint8_t* work;
+  hipStream_t stream;
+  double tau, rho_in, rho_out;
+  int parity;          // f[parity] holds the current state
+  int64_t steps;
+  int linear_eq;
+
+  uint32_t* links() const { return (uint32_t*)(work + L.off_links); }
+  void* bplane(int p) const { return work + L.off_bplane + (size_t)p * L.bplane_one * L.esize; }
+  double* partial() const { return (double*)(work + L.off_partial); }
+  double* scalar() const { return (double*)(work + L.off_scalar); }
+};
+
+namespace {
+
+template <class T>
+StepArgs<T> step_args(const lbm_ctx* c) {
+  StepArgs<T> a;
+  a.src = (const T*)c->f[c->parity];
+  a.dst = (T*)c->f[c->parity ^ 1];
+  a.links = c->links();
+  a.bp_src = (const T*)c->bplane(c->parity);
+  a.bp_dst = (T*)c->bplane(c->parity ^ 1);
+  a.partial = c->partial();
+  a.ps = c->L.ps;
+  a.nx = c->g.nx;
+  a.ny = c->g.ny;
+  a.nz = c->g.nz;
+  a.xp = c->L.xp;
+  a.tiles_x = c->L.tiles_x;
+  a.tiles_y = c->L.tiles_y;
+  a.omega = (T)(1.0 / c->tau);
+  a.rho0 = (T)c->g.rho0;
+  a.drho_in = (T)(c->rho_in - c->g.rho0);
+  a.drho_out = (T)(c->rho_out - c->g.rho0);
+  return a;
+}
+
+unsigned grid_1d(uint64_t n) { return (unsigned)((n + 255) / 256); }
+
+template <class Lat, class T>
+lbm_status launch_steps(lbm_ctx* c, int64_t n, bool flux_last) {
+  for (int64_t s = 0; s < n; ++s) {
+    StepArgs<T> a = step_args<T>(c);
+    const bool flux = flux_last && s == n - 1;
+    dim3 block(kTileX, kTileY);
+    if (c->linear_eq) {
+      if (flux) k_step<Lat, T, true, true><<<c->L.blocks, block, 0, c->stream>>>(a);
+      else k_step<Lat, T, false, true><<<c->L.blocks, block, 0, c->stream>>>(a);
+    } else {
+      if (flux) k_step<Lat, T, true, false><<<c->L.blocks, block, 0, c->stream>>>(a);
+      else k_step<Lat, T, false, false><<<c->L.blocks, block, 0, c->stream>>>(a);
+    }
+    c->parity ^= 1;
+    c->steps += 1;
+  }
+  HIP_TRY(hipGetLastError());
+  return LBM_OK;
+}
+
+template <class Lat, class T>
+lbm_status launch_bplane(lbm_ctx* c) {
+  const uint64_t n = 2ull * c->g.nz * c->g.ny;
+  k_bplane<Lat, T><<<grid_1d(n), 256, 0, c->stream>>>(
+      (const T*)c->f[c->parity], c->links(), (T*)c->bplane(c->parity), c->L.ps, c->g.nx,
+      c->g.ny, c->g.nz, c->L.xp, (T)c->g.rho0);
+  HIP_TRY(hipGetLastError());
+  return LBM_OK;
+}
+
+template <class Lat, class T>
+lbm_status launch_reset(lbm_ctx* c, int mode) {
+  k_init_rest<Lat, T><<<grid_1d(c->L.ps), 256, 0, c->stream>>>(
+      (T*)c->f[c->parity], (T*)c->f[c->parity ^ 1], c->links(), c->L.ps, c->g.nx, c->g.ny, c->g.nz, c->L.xp, mode,
+      c->rho_in, c->rho_out, c->g.rho0);
+  HIP_TRY(hipGetLastError());
+  return launch_bplane<Lat, T>(c);
+}
+
+template <class Lat, class T>
+lbm_status launch_fields(lbm_ctx* c, const float* rho, const float* u) {
+  k_init_fields<Lat, T><<<grid_1d(c->L.ps), 256, 0, c->stream>>>(
+      (T*)c->f[c->parity], c->links(), rho, u, c->L.ps, c->g.nx, c->g.ny, c->g.nz, c->L.xp,
+      c->g.rho0);
+  HIP_TRY(hipGetLastError());
+  return launch_bplane<Lat, T>(c);
+}
+
+template <class Lat, class T>
+lbm_status launch_flux(lbm_ctx* c) {
+  dim3 block(kTileX, kTileY);
+  k_flux<Lat, T><<<c->L.blocks, block, 0, c->stream>>>((const T*)c->f[c->parity], c->links(),
+                                                         c->partial(), c->L.ps, c->g.nx,
+                                                         c->g.ny, c->L.xp, c->L.tiles_x,
+                                                         c->L.tiles_y);
+  HIP_TRY(hipGetLastError());
+  return LBM_OK;
+}
+
+template <class Lat, class T>
+lbm_status launch_macro(lbm_ctx* c, void* rho, void* u, int dtype) {
+  const uint64_t N = (uint64_t)c->g.nx * c->g.ny * c->g.nz;
+  if (dtype == 0)
+    k_macro<Lat, T, float><<<grid_1d(N), 256, 0, c->stream>>>(
+        (const T*)c->f[c->parity], c->links(), (float*)rho, (float*)u, c->L.ps, c->g.nx,
+        c->g.ny, c->g.nz, c->L.xp, (T)c->g.rho0);
+  else
+    k_macro<Lat, T, double><<<grid_1d(N), 256, 0, c->stream>>>(
+        (const T*)c->f[c->parity], c->links(), (double*)rho, (double*)u, c->L.ps, c->g.nx,
+        c->g.ny, c->g.nz, c->L.xp, (T)c->g.rho0);
+  HIP_TRY(hipGetLastError());
+  return LBM_OK;
+}
+
+template <template <class, class> class F, class... A>
+lbm_status dispatch(lbm_ctx* c, A... args) {
+  if (c->g.lattice == LBM_D2Q9)
+    return c->g.precision == LBM_FP64 ? F<D2Q9, double>::run(c, args...)
+                                      : F<D2Q9, float>::run(c, args...);
+  return c->g.precision == LBM_FP64 ? F<D3Q19, double>::run(c, args...)
+                                    : F<D3Q19, float>::run(c, args...);
+}
+
+template <class Lat, class T> struct Steps {
+  static lbm_status run(lbm_ctx* c, int64_t n, bool fl) { return launch_steps<Lat, T>(c, n, fl); }
+};
+template <class Lat, class T> struct Reset {
+  static lbm_status run(lbm_ctx* c, int mode) { return launch_reset<Lat, T>(c, mode); }
+};
+template <class Lat, class T> struct Fields {
+  static lbm_status run(lbm_ctx* c, const float* r, const float* u) {
+    return launch_fields<Lat, T>(c, r, u);
+  }
+};
+template <class Lat, class T> struct Flux {
+  static lbm_status run(lbm_ctx* c) { return launch_flux<Lat, T>(c); }
+};
+template <class Lat, class T> struct Macro {
+  static lbm_status run(lbm_ctx* c, void* r, void* u, int d) { return launch_macro<Lat, T>(c, r, u, d); }
+};
+template <class Lat, class T> struct Bplane {
+  static lbm_status run(lbm_ctx* c) { return launch_bplane<Lat, T>(c); }
+};
+
+// Reduces the partials of the last flux pass into scalar[0] and reads it back.
+lbm_status reduce_flux(lbm_ctx* c, double* q) {
+  k_reduce<<<1, 256, 0, c->stream>>>(c->partial(), c->L.blocks, 1.0 / c->g.nx, c->scalar());
+  HIP_TRY(hipGetLastError());
+  double h = 0.0;
+  HIP_TRY(hipMemcpyAsync(&h, c->scalar(), sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  *q = h;
+  return LBM_OK;
+}
+
+lbm_status current_flux(lbm_ctx* c, double* q) {
+  lbm_status s = dispatch<Flux>(c);
+  if (s != LBM_OK) return s;
+  return reduce_flux(c, q);
+}
+
+double perm_from_flux(const lbm_ctx* c, double q) {
+  const double nu = (c->tau - 0.5) / 3.0;
+  const double L = c->g.nx + 1.0, A = (double)c->g.ny * c->g.nz;
+  return nu * q * L / (A * (1.0 / 3.0) * (c->rho_in - c->rho_out));
+}
+
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_query_sizes(const lbm_geom* geom, size_t* f_bytes, size_t* work_bytes) {
+  Layout L;
+  lbm_status s = make_layout(geom, &L);
+  if (s != LBM_OK) return s;
+  if (f_bytes) *f_bytes = L.f_bytes;
+  if (work_bytes) *work_bytes = L.work_bytes;
+  return ok();
+}
+
+lbm_status lbm_init(lbm_ctx** out, const lbm_geom* geom, const lbm_buffers* bufs, double tau,
+                    double rho_in, double rho_out) {
+  if (!out) return fail(LBM_EINVAL, "out is NULL");
+  *out = nullptr;
+  Layout L;
+  lbm_status s = make_layout(geom, &L);
+  if (s != LBM_OK) return s;
+  if (!bufs) return fail(LBM_EINVAL, "bufs is NULL");
+  if (!bufs->f[0] || !bufs->f[1] || !bufs->mask || !bufs->work)
+    return fail(LBM_EINVAL, "a device buffer is NULL");
+  if (bufs->f[0] == bufs->f[1]) return fail(LBM_EINVAL, "f[0] and f[1] must differ");
+  if (!(tau > 0.5) || !isfinite(tau))
+    return fail(LBM_EINVAL, "tau must be > 1/2 (positive viscosity), got %g", tau);
+  if (!(rho_in > 0.0) || !(rho_out > 0.0) || !isfinite(rho_in) || !isfinite(rho_out))
+    return fail(LBM_EINVAL, "rho_in and rho_out must be positive and finite");
+  if (((uintptr_t)bufs->f[0] | (uintptr_t)bufs->f[1] | (uintptr_t)bufs->work) & 255)
+    return fail(LBM_EINVAL, "f[0], f[1] and work must be 256-byte aligned");
+  lbm_ctx* c = new (std::nothrow) lbm_ctx();
+  if (!c) return fail(LBM_ENOMEM, "out of host memory");
+  c->g = *geom;
+  c->L = L;
+  c->f[0] = bufs->f[0];
+  c->f[1] = bufs->f[1];
+  c->mask = (const uint8_t*)bufs->mask;
+  c->work = (uint8_t*)bufs->work;
+  c->stream = (hipStream_t)bufs->stream;
+  c->tau = tau;
+  c->rho_in = rho_in;
+  c->rho_out = rho_out;
+  c->parity = 0;
+  c->steps = 0;
+  c->linear_eq = 0;
+
+  const uint64_t n_pad = L.ps;
+  auto fail_free = [&](lbm_status st) { delete c; return st; };
+  if (geom->lattice == LBM_D2Q9)
+    k_links<D2Q9><<<grid_1d(n_pad), 256, 0, c->stream>>>(c->mask, c->links(), geom->nx, geom->ny,
+                                                          geom->nz, L.xp);
+  else
+    k_links<D3Q19><<<grid_1d(n_pad), 256, 0, c->stream>>>(c->mask, c->links(), geom->nx, geom->ny,
+                                                           geom->nz, L.xp);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail_free(fail(LBM_EHIP, "link kernel: %s", hipGetErrorString(e)));
+  s = dispatch<Reset>(c, (int)LBM_START_UNIFORM);
+  if (s != LBM_OK) return fail_free(s);
+  *out = c;
+  return ok();
+}
+
+lbm_status lbm_reset(lbm_ctx* c, int32_t start) {
+  if (!c) return fail(LBM_EINVAL, "ctx is NULL");
+  if (start != LBM_START_UNIFORM && start != LBM_START_LINEAR)
+    return fail(LBM_EINVAL, "start must be LBM_START_UNIFORM or LBM_START_LINEAR");
+  c->parity = 0;
+  c->steps = 0;
+  lbm_status s = dispatch<Reset>(c, (int)start);
+  return s == LBM_OK ? ok() : s;
+}
+
+lbm_status lbm_set_macro(lbm_ctx* c, const float* rho, const float* u) {
+  if (!c) return fail(LBM_EINVAL, "ctx is NULL");
+  if (!rho || !u) return fail(LBM_EINVAL, "rho and u must be device pointers");
+  c->parity = 0;
+  c->steps = 0;
+  lbm_status s = dispatch<Fields>(c, rho, u);
+  return s == LBM_OK ? ok() : s;
+}
+
+lbm_status lbm_step(lbm_ctx* c, int64_t n) {
+  if (!c) return fail(LBM_EINVAL, "ctx is NULL");
+  if (n < 0) return fail(LBM_EINVAL, "n must be >= 0");
+  lbm_status s = dispatch<Steps>(c, n, false);
+  return s == LBM_OK ? ok() : s;
+}
+
+lbm_status lbm_flux(lbm_ctx* c, double* q_out) {
+  if (!c || !q_out) return fail(LBM_EINVAL, "NULL argument");
+  double q;
+  lbm_status s = current_flux(c, &q);
+  if (s != LBM_OK) return s;
+  *q_out = q;
+  if (!isfinite(q)) return fail(LBM_ENONFINITE, "flux is not finite");
+  return ok();
+}
+
+lbm_status lbm_permeability(lbm_ctx* c, double* k_out) {
+  if (!c || !k_out) return fail(LBM_EINVAL, "NULL argument");
+  if (c->rho_in == c->rho_out) return fail(LBM_ESTATE, "rho_in == rho_out: no pressure drop");
+  double q;
+  lbm_status s = current_flux(c, &q);
+  if (s != LBM_OK) return s;
+  if (!isfinite(q)) {
+    *k_out = q;
+    return fail(LBM_ENONFINITE, "flux is not finite");
+  }
+  if (q == 0.0) {
+    *k_out = 0.0;
+    return fail(LBM_ENOFLOW, "zero mass flow rate");
+  }
+  *k_out = perm_from_flux(c, q);
+  return ok();
+}
+
+lbm_status lbm_run_to_steady(lbm_ctx* c, double tol, int64_t max_steps, int64_t* steps_out,
+                             double* resid_out) {
+  if (!c) return fail(LBM_EINVAL, "ctx is NULL");
+  if (!(tol >= 0.0) || max_steps < 0) return fail(LBM_EINVAL, "need tol >= 0 and max_steps >= 0");
+  const int K = c->g.check_every;
+  double prev;
+  lbm_status s = current_flux(c, &prev);
+  if (s != LBM_OK) return s;
+  double r = INFINITY;
+  bool conv = false;
+  while (c->steps + K <= max_steps) {
+    s = dispatch<Steps>(c, (int64_t)K, true);
+    if (s != LBM_OK) return s;
+    double q;
+    s = reduce_flux(c, &q);
+    if (s != LBM_OK) return s;
+    if (!isfinite(q)) {
+      if (steps_out) *steps_out = c->steps;
+      if (resid_out) *resid_out = NAN;
+      return fail(LBM_ENONFINITE, "flux became non-finite after %lld steps", (long long)c->steps);
+    }
+    r = fabs(q - prev) / fabs(q);
+    prev = q;
+    if (r < tol) {
+      conv = true;
+      break;
+    }
+  }
+  if (steps_out) *steps_out = c->steps;
+  if (resid_out) *resid_out = r;
+  if (!conv)
+    return fail(LBM_ENOTCONV, "residual %g above %g after %lld steps", r, tol, (long long)c->steps);
+  return ok();
+}
+
+lbm_status lbm_get_macro(lbm_ctx* c, void* rho, void* u, int32_t dtype) {
+  if (!c || !rho || !u) return fail(LBM_EINVAL, "NULL argument");
+  if (dtype != 0 && dtype != 1) return fail(LBM_EINVAL, "dtype must be 0 (float32) or 1 (float64)");
+  lbm_status s = dispatch<Macro>(c, rho, u, (int)dtype);
+  return s == LBM_OK ? ok() : s;
+}
+
+lbm_status lbm_get_populations(lbm_ctx* c, void* dst) {
+  if (!c || !dst) return fail(LBM_EINVAL, "NULL argument");
+  HIP_TRY(hipMemcpyAsync(dst, c->f[c->parity], c->L.f_bytes, hipMemcpyDeviceToDevice, c->stream));
+  return ok();
+}
+
+lbm_status lbm_set_populations(lbm_ctx* c, const void* src) {
+  if (!c || !src) return fail(LBM_EINVAL, "NULL argument");
+  HIP_TRY(hipMemcpyAsync(c->f[c->parity], src, c->L.f_bytes, hipMemcpyDeviceToDevice, c->stream));
+  lbm_status s = dispatch<Bplane>(c);
+  return s == LBM_OK ? ok() : s;
+}
+
+lbm_status lbm_lattice(int32_t lattice, int32_t* cv, double* w) {
+  if (!cv || !w) return fail(LBM_EINVAL, "NULL argument");
+  if (lattice == LBM_D2Q9) {
+    for (int i = 0; i < D2Q9::Q; ++i) {
+      cv[3 * i] = D2Q9::cx[i]; cv[3 * i + 1] = D2Q9::cy[i]; cv[3 * i + 2] = D2Q9::cz[i];
+      w[i] = D2Q9::w[i];
+    }
+  } else if (lattice == LBM_D3Q19) {
+    for (int i = 0; i < D3Q19::Q; ++i) {
+      cv[3 * i] = D3Q19::cx[i]; cv[3 * i + 1] = D3Q19::cy[i]; cv[3 * i + 2] = D3Q19::cz[i];
+      w[i] = D3Q19::w[i];
+    }
+  } else {
+    return fail(LBM_EINVAL, "lattice must be 9 or 19");
+  }
+  return ok();
+}
+
+lbm_status lbm_steps(const lbm_ctx* c, int64_t* steps_out) {
+  if (!c || !steps_out) return fail(LBM_EINVAL, "NULL argument");
+  *steps_out = c->steps;
+  return ok();
+}
+
+double lbm_knudsen(double tau, int32_t nx) { return sqrt(M_PI / 6.0) * (tau - 0.5) / (double)nx; }
+
+lbm_status lbm_destroy(lbm_ctx* c) {
+  delete c;
+  return ok();
+}
+
+const char* lbm_last_error(void) { return g_err; }
+
+const char* lbm_version(void) { return "1.0.0"; }
+
+}  // extern "C"

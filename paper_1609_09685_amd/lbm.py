@@ -1,0 +1,241 @@
+"""Python binding of the C ABI in ``include/lbm.h`` (argument marshalling only).
+
+Every step of the solver runs in the HIP library ``liblbm.so``; torch only
+allocates the device buffers the library asks for and supplies the stream.
+There is no CPU fallback: importing this module without the built library, or
+constructing a solver without a GPU, raises.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+LBM_OK, LBM_EINVAL, LBM_EHIP, LBM_ENOMEM = 0, -1, -2, -3
+LBM_ENONFINITE, LBM_ENOTCONV, LBM_ENOFLOW, LBM_ESTATE = -4, -5, -6, -7
+LBM_D2Q9, LBM_D3Q19 = 9, 19
+LBM_FP64, LBM_FP32 = 0, 1
+_PRECISION = {"fp64": LBM_FP64, "fp32": LBM_FP32}
+_START = {"uniform": 0, "linear": 1}
+
+
+class LBMError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"[{status}] {message}")
+        self.status = status
+        self.message = message
+
+
+class Geom(ctypes.Structure):
+    _fields_ = [("lattice", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("nz", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("check_every", ctypes.c_int32), ("rho0", ctypes.c_double)]
+
+
+class Buffers(ctypes.Structure):
+    _fields_ = [("f", ctypes.c_void_p * 2), ("mask", ctypes.c_void_p), ("work", ctypes.c_void_p),
+                ("stream", ctypes.c_void_p)]
+
+
+_lib = None
+
+# name -> (restype, argtypes) for every entry point of include/lbm.h
+_c = ctypes
+_SIGS = {
+    "lbm_query_sizes": (_c.c_int, [_c.POINTER(Geom), _c.POINTER(_c.c_size_t), _c.POINTER(_c.c_size_t)]),
+    "lbm_init": (_c.c_int, [_c.POINTER(_c.c_void_p), _c.POINTER(Geom), _c.POINTER(Buffers),
+                            _c.c_double, _c.c_double, _c.c_double]),
+    "lbm_reset": (_c.c_int, [_c.c_void_p, _c.c_int32]),
+    "lbm_set_macro": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p]),
+    "lbm_step": (_c.c_int, [_c.c_void_p, _c.c_int64]),
+    "lbm_flux": (_c.c_int, [_c.c_void_p, _c.POINTER(_c.c_double)]),
+    "lbm_permeability": (_c.c_int, [_c.c_void_p, _c.POINTER(_c.c_double)]),
+    "lbm_run_to_steady": (_c.c_int, [_c.c_void_p, _c.c_double, _c.c_int64,
+                                     _c.POINTER(_c.c_int64), _c.POINTER(_c.c_double)]),
+    "lbm_get_macro": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_int32]),
+    "lbm_get_populations": (_c.c_int, [_c.c_void_p, _c.c_void_p]),
+    "lbm_set_populations": (_c.c_int, [_c.c_void_p, _c.c_void_p]),
+    "lbm_lattice": (_c.c_int, [_c.c_int32, _c.c_void_p, _c.c_void_p]),
+    "lbm_steps": (_c.c_int, [_c.c_void_p, _c.POINTER(_c.c_int64)]),
+    "lbm_knudsen": (_c.c_double, [_c.c_double, _c.c_int32]),
+    "lbm_destroy": (_c.c_int, [_c.c_void_p]),
+    "lbm_last_error": (_c.c_char_p, []),
+    "lbm_version": (_c.c_char_p, []),
+}
+
+
+def library_path():
+    return _build.LBM_LIB
+
+
+def load_library():
+    """Loads liblbm.so; raises ImportError if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = library_path()
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_1609_09685_amd.build`"
+                          " (the solver has no CPU fallback)")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status, allow=()):
+    if status != LBM_OK and status not in allow:
+        msg = load_library().lbm_last_error().decode(errors="replace")
+        raise LBMError(status, msg)
+    return status
+
+
+def query_sizes(lattice, nx, ny, nz, precision="fp32", check_every=100, rho0=1.0):
+    g = Geom(lattice, nx, ny, nz, _PRECISION[precision], check_every, rho0)
+    fb, wb = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    _check(load_library().lbm_query_sizes(ctypes.byref(g), ctypes.byref(fb), ctypes.byref(wb)))
+    return fb.value, wb.value
+
+
+def lattice_table(lattice):
+    """(c, w) of the library's internal direction order."""
+    q = int(lattice)
+    c = np.zeros((q, 3), np.int32)
+    w = np.zeros(q)
+    _check(load_library().lbm_lattice(q, c.ctypes.data, w.ctypes.data))
+    return c, w
+
+
+def knudsen(tau, nx):
+    return float(load_library().lbm_knudsen(float(tau), int(nx)))
+
+
+class Solver:
+    """One porous domain on one GPU.
+
+    mask: uint8 array, (ny, nx) for D2Q9 or (nz, ny, nx) for D3Q19, 1 = solid.
+    precision: "fp64" or "fp32" (populations stored as deviations from rest).
+    """
+
+    def __init__(self, mask, tau, rho_in, rho_out, precision="fp32", lattice=None,
+                 check_every=100, rho0=1.0, device="cuda", stream=None):
+        import torch
+
+        lib = load_library()
+        if not torch.cuda.is_available():
+            raise RuntimeError("the lattice Boltzmann solver needs a GPU (HIP device)")
+        m = np.ascontiguousarray(mask, np.uint8)
+        if lattice is None:
+            lattice = LBM_D2Q9 if m.ndim == 2 else LBM_D3Q19
+        if m.ndim == 2:
+            m = m[None]
+        if m.ndim != 3:
+            raise ValueError("mask must be 2D or 3D")
+        self.nz, self.ny, self.nx = (int(s) for s in m.shape)
+        self.lattice = int(lattice)
+        self.precision = precision
+        self.tau, self.rho_in, self.rho_out = float(tau), float(rho_in), float(rho_out)
+        self.D = 2 if self.lattice == LBM_D2Q9 else 3
+        self.device = torch.device(device)
+        self._geom = Geom(self.lattice, self.nx, self.ny, self.nz, _PRECISION[precision],
+                          int(check_every), float(rho0))
+        fb, wb = ctypes.c_size_t(0), ctypes.c_size_t(0)
+        _check(lib.lbm_query_sizes(ctypes.byref(self._geom), ctypes.byref(fb), ctypes.byref(wb)))
+        self.f_bytes, self.work_bytes = fb.value, wb.value
+        self._f = [torch.empty(self.f_bytes, dtype=torch.uint8, device=self.device) for _ in range(2)]
+        self._work = torch.empty(self.work_bytes, dtype=torch.uint8, device=self.device)
+        self._mask = torch.from_numpy(m.reshape(-1).copy()).to(self.device)
+        self._stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        bufs = Buffers()
+        bufs.f[0] = self._f[0].data_ptr()
+        bufs.f[1] = self._f[1].data_ptr()
+        bufs.mask = self._mask.data_ptr()
+        bufs.work = self._work.data_ptr()
+        bufs.stream = self._stream.cuda_stream
+        self._bufs = bufs
+        h = ctypes.c_void_p(0)
+        _check(lib.lbm_init(ctypes.byref(h), ctypes.byref(self._geom), ctypes.byref(bufs),
+                            self.tau, self.rho_in, self.rho_out))
+        self._h = h
+        self._lib = lib
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._lib.lbm_destroy(h)
+            self._h = None
+
+    __del__ = close
+
+    # -- state --------------------------------------------------------------
+    def reset(self, start="uniform"):
+        _check(self._lib.lbm_reset(self._h, _START[start]))
+
+    def set_macro(self, rho, u):
+        """Start from f = f_eq(rho, u); rho (nz,ny,nx) / u (D,nz,ny,nx) float32 device tensors."""
+        import torch
+        rho = rho.to(self.device, torch.float32).contiguous()
+        u = u.to(self.device, torch.float32).contiguous()
+        if rho.numel() != self.nx * self.ny * self.nz or u.numel() != self.D * rho.numel():
+            raise ValueError("rho / u have the wrong number of elements")
+        _check(self._lib.lbm_set_macro(self._h, rho.data_ptr(), u.data_ptr()))
+        self._keep = (rho, u)  # kept alive until the stream has consumed them
+
+    def step(self, n=1):
+        _check(self._lib.lbm_step(self._h, int(n)))
+
+    @property
+    def steps(self):
+        s = ctypes.c_int64(0)
+        _check(self._lib.lbm_steps(self._h, ctypes.byref(s)))
+        return s.value
+
+    def flux(self):
+        q = ctypes.c_double(0.0)
+        _check(self._lib.lbm_flux(self._h, ctypes.byref(q)))
+        return q.value
+
+    def permeability(self):
+        k = ctypes.c_double(0.0)
+        _check(self._lib.lbm_permeability(self._h, ctypes.byref(k)))
+        return k.value
+
+    def run_to_steady(self, tol=1e-9, max_steps=10**6, raise_on_notconv=True):
+        """Returns (converged, steps, residual)."""
+        s, r = ctypes.c_int64(0), ctypes.c_double(0.0)
+        st = self._lib.lbm_run_to_steady(self._h, float(tol), int(max_steps), ctypes.byref(s),
+                                         ctypes.byref(r))
+        _check(st, allow=() if raise_on_notconv else (LBM_ENOTCONV,))
+        return st == LBM_OK, s.value, r.value
+
+    def macro(self, dtype="float64"):
+        """(rho (nz,ny,nx), u (D,nz,ny,nx)) as device tensors; solids rho0 and 0."""
+        import torch
+        td = torch.float64 if dtype == "float64" else torch.float32
+        rho = torch.empty((self.nz, self.ny, self.nx), dtype=td, device=self.device)
+        u = torch.empty((self.D, self.nz, self.ny, self.nx), dtype=td, device=self.device)
+        _check(self._lib.lbm_get_macro(self._h, rho.data_ptr(), u.data_ptr(),
+                                       1 if td == torch.float64 else 0))
+        return rho, u
+
+    def get_populations(self):
+        import torch
+        out = torch.empty(self.f_bytes, dtype=torch.uint8, device=self.device)
+        _check(self._lib.lbm_get_populations(self._h, out.data_ptr()))
+        return out
+
+    def set_populations(self, buf):
+        if buf.numel() * buf.element_size() != self.f_bytes:
+            raise ValueError("population buffer has the wrong size")
+        _check(self._lib.lbm_set_populations(self._h, buf.data_ptr()))
+        self._keep = buf
+
+    def knudsen(self):
+        return knudsen(self.tau, self.nx)
+
+    def synchronize(self):
+        self._stream.synchronize()

@@ -1,0 +1,140 @@
+"""C ABI checks that need no GPU: the library loads, exports every entry point
+that include/*.h declares, and rejects bad arguments before any HIP call."""
+import ctypes
+import glob
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1609_09685_amd import lbm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared(header):
+    text = open(header).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b((?:lbm|wsn)_[a-z0-9_]+)\s*\(", text)))
+
+
+def _nm_exports(path):
+    import subprocess
+    out = subprocess.run(["nm", "-D", "--defined-only", path], capture_output=True, text=True,
+                         check=True).stdout
+    return {ln.split()[-1] for ln in out.splitlines() if ln.strip()}
+
+
+@pytest.mark.parametrize("header", sorted(glob.glob(os.path.join(ROOT, "include", "*.h"))))
+def test_every_declared_symbol_is_exported(header):
+    names = declared(header)
+    assert names
+    path = lbm.library_path()
+    exported = _nm_exports(path)
+    missing = [n for n in names if n not in exported]
+    assert not missing, f"{os.path.basename(header)}: not exported: {missing}"
+    lib = ctypes.CDLL(path)
+    for n in names:
+        getattr(lib, n)
+
+
+def test_binding_covers_header():
+    names = declared(os.path.join(ROOT, "include", "lbm.h"))
+    assert set(names) == set(lbm._SIGS)
+
+
+def _geom(**kw):
+    d = dict(lattice=9, nx=100, ny=50, nz=1, precision=lbm.LBM_FP64, check_every=100, rho0=1.0)
+    d.update(kw)
+    return lbm.Geom(**d)
+
+
+def _status(g):
+    fb, wb = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    return lbm.load_library().lbm_query_sizes(ctypes.byref(g), ctypes.byref(fb), ctypes.byref(wb)), \
+        fb.value, wb.value
+
+
+@pytest.mark.parametrize("kw", [dict(lattice=7), dict(nz=2), dict(nx=1), dict(ny=0),
+                                dict(precision=5), dict(check_every=0), dict(rho0=0.0),
+                                dict(rho0=float("nan")),
+                                dict(lattice=19, nx=2048, ny=2048, nz=1024)])
+def test_query_sizes_rejects(kw):
+    st, _, _ = _status(_geom(**kw))
+    assert st == lbm.LBM_EINVAL
+    assert lbm.load_library().lbm_last_error()
+
+
+@pytest.mark.parametrize("lat,prec,nx,ny,nz,esize,pitch", [
+    (9, lbm.LBM_FP64, 100, 50, 1, 8, 112), (9, lbm.LBM_FP32, 100, 50, 1, 4, 128),
+    (19, lbm.LBM_FP32, 512, 512, 512, 4, 512), (19, lbm.LBM_FP64, 33, 7, 5, 8, 48)])
+def test_query_sizes_layout(lat, prec, nx, ny, nz, esize, pitch):
+    st, fb, wb = _status(_geom(lattice=lat, precision=prec, nx=nx, ny=ny, nz=nz))
+    assert st == lbm.LBM_OK
+    assert fb == lat * nz * ny * pitch * esize          # SoA, x pitch padded to 128 B
+    assert wb >= nz * ny * pitch * 4                    # one link word per padded node
+
+
+def test_init_validates_before_any_hip_call():
+    lib = lbm.load_library()
+    g = _geom()
+    fake = 1 << 20  # never dereferenced: every call below must fail validation first
+    bufs = lbm.Buffers()
+    bufs.f[0], bufs.f[1], bufs.mask, bufs.work, bufs.stream = fake, fake * 2, fake * 3, fake * 4, 0
+    h = ctypes.c_void_p(0)
+    cases = [
+        (dict(tau=0.5, ri=1.0, ro=1.0), "tau"),
+        (dict(tau=0.2, ri=1.0, ro=1.0), "tau"),
+        (dict(tau=float("nan"), ri=1.0, ro=1.0), "tau"),
+        (dict(tau=0.8, ri=0.0, ro=1.0), "rho"),
+        (dict(tau=0.8, ri=1.0, ro=-1.0), "rho"),
+    ]
+    for kw, word in cases:
+        st = lib.lbm_init(ctypes.byref(h), ctypes.byref(g), ctypes.byref(bufs), kw["tau"], kw["ri"], kw["ro"])
+        assert st == lbm.LBM_EINVAL
+        assert word in lib.lbm_last_error().decode()
+        assert not h.value
+    nb = lbm.Buffers()
+    st = lib.lbm_init(ctypes.byref(h), ctypes.byref(g), ctypes.byref(nb), 0.8, 1.0, 1.0)
+    assert st == lbm.LBM_EINVAL
+    same = lbm.Buffers()
+    same.f[0], same.f[1], same.mask, same.work = fake, fake, fake, fake
+    assert lib.lbm_init(ctypes.byref(h), ctypes.byref(g), ctypes.byref(same), 0.8, 1.0, 1.0) == lbm.LBM_EINVAL
+    odd = lbm.Buffers()
+    odd.f[0], odd.f[1], odd.mask, odd.work = fake + 4, fake * 2, fake, fake * 4
+    assert lib.lbm_init(ctypes.byref(h), ctypes.byref(g), ctypes.byref(odd), 0.8, 1.0, 1.0) == lbm.LBM_EINVAL
+    assert lib.lbm_step(None, 1) == lbm.LBM_EINVAL
+    assert lib.lbm_destroy(None) == lbm.LBM_OK
+
+
+@pytest.mark.parametrize("Q", [9, 19])
+def test_library_lattice_tables(Q):
+    """The solver's own direction tables satisfy the lattice identities."""
+    c, w = lbm.lattice_table(Q)
+    c = c.astype(float)
+    d = 2 if Q == 9 else 3
+    assert len({tuple(v) for v in c}) == Q
+    assert math.isclose(w.sum(), 1.0, rel_tol=1e-15)
+    assert np.allclose(w @ c, 0, atol=1e-16)
+    assert np.allclose(np.einsum("i,ia,ib->ab", w, c, c)[:d, :d], np.eye(d) / 3, atol=1e-15)
+    four = np.einsum("i,ia,ib,ic,id->abcd", w, c, c, c, c)
+    e = np.eye(3)
+    iso = (np.einsum("ab,cd->abcd", e, e) + np.einsum("ac,bd->abcd", e, e)
+           + np.einsum("ad,bc->abcd", e, e)) / 9
+    assert np.allclose(four[:d, :d, :d, :d], iso[:d, :d, :d, :d], atol=1e-15)
+
+
+def test_knudsen():
+    for tau, nx in [(0.51, 400), (2.0, 1200), (0.8, 100)]:
+        assert lbm.knudsen(tau, nx) == pytest.approx(math.sqrt(math.pi / 6) * (tau - 0.5) / nx,
+                                                     rel=1e-15)
+
+
+def test_solver_refuses_without_gpu():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(RuntimeError):
+        lbm.Solver(np.zeros((4, 8), np.uint8), 0.8, 1.001, 0.999)
