@@ -76,6 +76,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="d3q19_512_fp32", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--xcd-remap", type=int, default=1, choices=[0, 1])
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU runs are not "
@@ -91,6 +92,7 @@ def main():
     log(f"mask {shape} porosity {1 - mask.mean():.4f} in {time.time() - t0:.1f} s")
     torch.cuda.set_device(0)
     s = lbm.Solver(mask, tau, rin, rout, precision=prec, lattice=Q)
+    s.set_xcd_remap(bool(args.xcd_remap))
     N = int(mask.size)
     n_fluid = int((mask == 0).sum())
     esize = 8 if prec == "fp64" else 4

@@ -39,11 +39,12 @@
  *   - One context may be driven by one host thread at a time; distinct
  *     contexts are independent.
  *
- * Storage: populations are kept as deviations from the rest state,
- * g_i = f_i - w_i rho0, population-major ("SoA"): g[i][z][y][x] with the x
- * pitch padded to a multiple of 128 bytes, so that the tiny Stokes-regime
- * pressure differences survive FP32 rounding.  The solid mask is uint8,
- * [nz][ny][nx] with x fastest, 1 = solid, 0 = fluid.
+ * Storage: populations are kept for fluid nodes only, as deviations from the
+ * rest state, g_i = f_i - w_i rho0 (so that the tiny Stokes-regime pressure
+ * differences survive FP32 rounding), direction-major: g[i][k] where k numbers
+ * the fluid nodes in x-fastest order (x, then y, then z) and each direction's
+ * array holds n_fluid rounded up to a multiple of 64 entries.  The solid mask
+ * is uint8, [nz][ny][nx] with x fastest, 1 = solid, 0 = fluid.
  */
 #ifndef LBM_H_
 #define LBM_H_
@@ -69,6 +70,10 @@ typedef enum {
 enum { LBM_D2Q9 = 9, LBM_D3Q19 = 19 };
 enum { LBM_FP64 = 0, LBM_FP32 = 1 };          /* storage and in-kernel arithmetic */
 enum { LBM_START_UNIFORM = 0, LBM_START_LINEAR = 1 };
+enum {
+  LBM_OPT_XCD_REMAP = 1,  /* 1 (default): deal consecutive tiles to one XCD; 0: hardware order */
+  LBM_OPT_LINEAR_EQ = 2   /* 1: equilibrium without the terms quadratic in u (Stokes); 0 (default) */
+};
 
 typedef struct lbm_ctx lbm_ctx;               /* opaque; host metadata only */
 
@@ -78,13 +83,14 @@ typedef struct {
   int32_t precision;    /* LBM_FP64 or LBM_FP32                                    */
   int32_t check_every;  /* K: steps between two convergence checks (>= 1)          */
   double rho0;          /* reference density of the deviation storage (> 0)        */
+  int64_t n_fluid;      /* number of fluid (0) voxels in the mask; lbm_init checks it */
 } lbm_geom;
 
 typedef struct {
   void *f[2];           /* two population buffers, f_bytes each (ping-pong)        */
   const void *mask;     /* device uint8 [nz][ny][nx], 1 = solid; read at init only */
-  void *work;           /* device scratch of work_bytes: link masks, boundary-plane
-                           moments, reduction partials                             */
+  void *work;           /* device scratch of work_bytes: fluid bitmap and prefix
+                           counts, boundary-plane moments, reduction partials      */
   void *stream;         /* hipStream_t the context enqueues on                     */
 } lbm_buffers;
 
@@ -94,8 +100,10 @@ lbm_status lbm_query_sizes(const lbm_geom *geom, size_t *f_bytes, size_t *work_b
 
 /* Creates a context and starts from rest with uniform density
  * (rho_in + rho_out)/2 (zero-velocity start).  Requires tau > 1/2 (positive
- * viscosity, Eq. 1), rho_in > 0, rho_out > 0, non-NULL buffers.  Enqueues the
- * set-up kernels; does not synchronise. */
+ * viscosity, Eq. 1), rho_in > 0, rho_out > 0, non-NULL 256-byte aligned
+ * buffers, and a mask with exactly geom->n_fluid fluid voxels (LBM_EINVAL
+ * otherwise).  Builds the fluid bitmap on the device and synchronises the
+ * stream once to check the fluid count. */
 lbm_status lbm_init(lbm_ctx **out, const lbm_geom *geom, const lbm_buffers *bufs,
                     double tau, double rho_in, double rho_out);
 
@@ -135,10 +143,13 @@ lbm_status lbm_run_to_steady(lbm_ctx *ctx, double tol, int64_t max_steps,
 lbm_status lbm_get_macro(lbm_ctx *ctx, void *rho, void *u, int32_t dtype);
 
 /* Checkpoint / restore: copies the current population buffer (f_bytes, the
- * library's internal layout and direction order) to / from device memory.
- * lbm_set_populations keeps the step count. */
+ * compact layout above, in the direction order of lbm_lattice) to / from
+ * device memory.  lbm_set_populations keeps the step count. */
 lbm_status lbm_get_populations(lbm_ctx *ctx, void *dst);
 lbm_status lbm_set_populations(lbm_ctx *ctx, const void *src);
+
+/* Tuning and model options (LBM_OPT_*); take effect at the next step. */
+lbm_status lbm_set_option(lbm_ctx *ctx, int32_t option, int64_t value);
 
 /* Direction table of the internal order: c[3*Q] (x,y,z per direction) and
  * w[Q].  Q = 9 or 19. */

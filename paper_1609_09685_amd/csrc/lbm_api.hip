@@ -3,10 +3,13 @@
 // A context holds host metadata only: the geometry, the physical parameters,
 // the caller's buffers and stream, the ping-pong parity and the step count.
 // Device memory is the caller's; the work buffer is carved here into
-//   links    uint32 [nz][ny][xp]             per-node link words
+//   bits     uint64 [nz][ny][nw + 2]     fluid bitmap with guard words
+//   pfx      uint32 [nz][ny][nw]         compact index of each word's first fluid node
+//   count    uint32 [nz][ny][nw]         fluid nodes per word (set-up only)
+//   scan     uint32 [scan blocks]        block totals of the prefix scan (set-up only)
 //   bplane   T [2 parities][2 sides][D+1][nz][ny]   edge-node moments
-//   partial  double [step blocks]             flux partials
-//   scalars  double [8]                       reduced flux, ...
+//   partial  double [...]                flux partials
+//   scalars  double [8]                  reduced flux, fluid count
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdarg.h>
@@ -50,12 +53,16 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 struct Layout {
   int Q, D;
   size_t esize;          // bytes per population value
-  int xp;                // padded x pitch (elements)
-  uint64_t ps;           // elements per population array
+  int nw;                // bitmap words per row
+  uint64_t rows;         // ny * nz
+  uint64_t n_fluid;
+  uint64_t ps;           // elements per direction array (n_fluid padded to 64)
   size_t f_bytes;
-  int tiles_x, tiles_y, blocks;
-  size_t off_links, off_bplane, off_partial, off_scalar, work_bytes;
+  int tiles_y, blocks, grid;   // step tiles; grid = blocks rounded up to 8 (XCD remap)
+  int scan_blocks;
+  size_t off_bits, off_pfx, off_count, off_scan, off_bplane, off_partial, off_scalar, work_bytes;
   size_t bplane_one;     // elements of one parity of the boundary-plane array
+  int partials;          // capacity of the partial array
 };
 
 lbm_status validate_geom(const lbm_geom* g) {
@@ -69,6 +76,9 @@ lbm_status validate_geom(const lbm_geom* g) {
   if (g->lattice == LBM_D2Q9 && g->nz != 1) return fail(LBM_EINVAL, "D2Q9 needs nz == 1");
   if (g->check_every < 1) return fail(LBM_EINVAL, "check_every must be >= 1");
   if (!(g->rho0 > 0.0) || !isfinite(g->rho0)) return fail(LBM_EINVAL, "rho0 must be > 0");
+  const uint64_t N = (uint64_t)g->nx * g->ny * g->nz;
+  if (g->n_fluid < 0 || (uint64_t)g->n_fluid > N)
+    return fail(LBM_EINVAL, "n_fluid must be in [0, nx*ny*nz], got %lld", (long long)g->n_fluid);
   return LBM_OK;
 }
 
@@ -78,27 +88,37 @@ lbm_status make_layout(const lbm_geom* g, Layout* L) {
   L->Q = g->lattice;
   L->D = g->lattice == LBM_D2Q9 ? 2 : 3;
   L->esize = g->precision == LBM_FP64 ? 8 : 4;
-  const int per_line = (int)(128 / L->esize);
-  L->xp = (int)align_up((size_t)g->nx, (size_t)per_line);
-  const uint64_t n_pad = (uint64_t)g->nz * g->ny * L->xp;
-  if (n_pad * L->esize >= (1ull << 32) || n_pad * 4 >= (1ull << 32))
-    return fail(LBM_EINVAL, "domain too large: %llu padded nodes exceed 32-bit byte offsets",
-                (unsigned long long)n_pad);
-  L->ps = n_pad;
-  L->f_bytes = (size_t)L->Q * n_pad * L->esize;
-  L->tiles_x = (g->nx + kTileX - 1) / kTileX;
-  L->tiles_y = (g->ny + kTileY - 1) / kTileY;
-  const uint64_t blocks = (uint64_t)L->tiles_x * L->tiles_y * g->nz;
-  if (blocks >= (1ull << 31)) return fail(LBM_EINVAL, "too many blocks");
+  L->nw = (g->nx + kWave - 1) / kWave;
+  L->rows = (uint64_t)g->ny * g->nz;
+  L->n_fluid = (uint64_t)g->n_fluid;
+  L->ps = align_up(L->n_fluid ? L->n_fluid : 1, 64);
+  if (L->ps >= (1ull << 32) || (uint64_t)g->nx * g->ny * g->nz >= (1ull << 40))
+    return fail(LBM_EINVAL, "domain too large: more than 2^32 fluid nodes");
+  L->f_bytes = (size_t)L->Q * L->ps * L->esize;
+  L->tiles_y = (g->ny + kRows - 1) / kRows;
+  const uint64_t blocks = (uint64_t)L->nw * L->tiles_y * g->nz;
+  if (blocks >= (1ull << 31) - 8) return fail(LBM_EINVAL, "too many blocks");
   L->blocks = (int)blocks;
+  L->grid = (int)align_up(blocks, 8);
+  const uint64_t nwords = L->rows * L->nw;
+  L->scan_blocks = (int)((nwords + kScanBlock - 1) / kScanBlock);
+  const uint64_t flux_blocks = (L->n_fluid + 255) / 256;
+  L->partials = (int)(blocks > flux_blocks ? blocks : flux_blocks);
+  if (L->partials < 1) L->partials = 1;
   L->bplane_one = (size_t)2 * (L->D + 1) * g->nz * g->ny;
   size_t off = 0;
-  L->off_links = off;
-  off = align_up(off + n_pad * 4, 256);
+  L->off_bits = off;
+  off = align_up(off + L->rows * (L->nw + 2) * 8, 256);
+  L->off_pfx = off;
+  off = align_up(off + nwords * 4, 256);
+  L->off_count = off;
+  off = align_up(off + nwords * 4, 256);
+  L->off_scan = off;
+  off = align_up(off + (size_t)L->scan_blocks * 4, 256);
   L->off_bplane = off;
   off = align_up(off + 2 * L->bplane_one * L->esize, 256);
   L->off_partial = off;
-  off = align_up(off + (size_t)L->blocks * 8, 256);
+  off = align_up(off + (size_t)L->partials * 8, 256);
   L->off_scalar = off;
   off = align_up(off + 64, 256);
   L->work_bytes = off;
@@ -118,11 +138,25 @@ struct lbm_ctx {
   int parity;          // f[parity] holds the current state
   int64_t steps;
   int linear_eq;
+  int xcd_remap;
 
-  uint32_t* links() const { return (uint32_t*)(work + L.off_links); }
+  uint64_t* bits() const { return (uint64_t*)(work + L.off_bits); }
+  uint32_t* pfx() const { return (uint32_t*)(work + L.off_pfx); }
+  uint32_t* count() const { return (uint32_t*)(work + L.off_count); }
+  uint32_t* scan() const { return (uint32_t*)(work + L.off_scan); }
   void* bplane(int p) const { return work + L.off_bplane + (size_t)p * L.bplane_one * L.esize; }
   double* partial() const { return (double*)(work + L.off_partial); }
   double* scalar() const { return (double*)(work + L.off_scalar); }
+  FluidMap fmap() const {
+    FluidMap m;
+    m.bits = bits();
+    m.pfx = pfx();
+    m.nx = g.nx;
+    m.ny = g.ny;
+    m.nz = g.nz;
+    m.nw = L.nw;
+    return m;
+  }
 };
 
 namespace {
@@ -132,17 +166,14 @@ StepArgs<T> step_args(const lbm_ctx* c) {
   StepArgs<T> a;
   a.src = (const T*)c->f[c->parity];
   a.dst = (T*)c->f[c->parity ^ 1];
-  a.links = c->links();
+  a.fm = c->fmap();
   a.bp_src = (const T*)c->bplane(c->parity);
   a.bp_dst = (T*)c->bplane(c->parity ^ 1);
   a.partial = c->partial();
   a.ps = c->L.ps;
-  a.nx = c->g.nx;
-  a.ny = c->g.ny;
-  a.nz = c->g.nz;
-  a.xp = c->L.xp;
-  a.tiles_x = c->L.tiles_x;
   a.tiles_y = c->L.tiles_y;
+  a.blocks = c->L.blocks;
+  a.xcd_remap = c->xcd_remap;
   a.omega = (T)(1.0 / c->tau);
   a.rho0 = (T)c->g.rho0;
   a.drho_in = (T)(c->rho_in - c->g.rho0);
@@ -151,19 +182,21 @@ StepArgs<T> step_args(const lbm_ctx* c) {
 }
 
 unsigned grid_1d(uint64_t n) { return (unsigned)((n + 255) / 256); }
+uint64_t n_nodes(const lbm_ctx* c) { return (uint64_t)c->g.nx * c->g.ny * c->g.nz; }
 
 template <class Lat, class T>
 lbm_status launch_steps(lbm_ctx* c, int64_t n, bool flux_last) {
+  const dim3 block(kWave, kRows);
+  const int grid = c->xcd_remap ? c->L.grid : c->L.blocks;
   for (int64_t s = 0; s < n; ++s) {
     StepArgs<T> a = step_args<T>(c);
     const bool flux = flux_last && s == n - 1;
-    dim3 block(kTileX, kTileY);
     if (c->linear_eq) {
-      if (flux) k_step<Lat, T, true, true><<<c->L.blocks, block, 0, c->stream>>>(a);
-      else k_step<Lat, T, false, true><<<c->L.blocks, block, 0, c->stream>>>(a);
+      if (flux) k_step<Lat, T, true, true><<<grid, block, 0, c->stream>>>(a);
+      else k_step<Lat, T, false, true><<<grid, block, 0, c->stream>>>(a);
     } else {
-      if (flux) k_step<Lat, T, true, false><<<c->L.blocks, block, 0, c->stream>>>(a);
-      else k_step<Lat, T, false, false><<<c->L.blocks, block, 0, c->stream>>>(a);
+      if (flux) k_step<Lat, T, true, false><<<grid, block, 0, c->stream>>>(a);
+      else k_step<Lat, T, false, false><<<grid, block, 0, c->stream>>>(a);
     }
     c->parity ^= 1;
     c->steps += 1;
@@ -176,52 +209,49 @@ template <class Lat, class T>
 lbm_status launch_bplane(lbm_ctx* c) {
   const uint64_t n = 2ull * c->g.nz * c->g.ny;
   k_bplane<Lat, T><<<grid_1d(n), 256, 0, c->stream>>>(
-      (const T*)c->f[c->parity], c->links(), (T*)c->bplane(c->parity), c->L.ps, c->g.nx,
-      c->g.ny, c->g.nz, c->L.xp, (T)c->g.rho0);
+      (const T*)c->f[c->parity], c->fmap(), (T*)c->bplane(c->parity), c->L.ps, (T)c->g.rho0);
   HIP_TRY(hipGetLastError());
   return LBM_OK;
 }
 
 template <class Lat, class T>
 lbm_status launch_reset(lbm_ctx* c, int mode) {
-  k_init_rest<Lat, T><<<grid_1d(c->L.ps), 256, 0, c->stream>>>(
-      (T*)c->f[c->parity], (T*)c->f[c->parity ^ 1], c->links(), c->L.ps, c->g.nx, c->g.ny, c->g.nz, c->L.xp, mode,
-      c->rho_in, c->rho_out, c->g.rho0);
+  k_init_rest<Lat, T><<<grid_1d(n_nodes(c)), 256, 0, c->stream>>>(
+      (T*)c->f[c->parity], (T*)c->f[c->parity ^ 1], c->fmap(), c->L.ps, mode, c->rho_in,
+      c->rho_out, c->g.rho0);
   HIP_TRY(hipGetLastError());
   return launch_bplane<Lat, T>(c);
 }
 
 template <class Lat, class T>
 lbm_status launch_fields(lbm_ctx* c, const float* rho, const float* u) {
-  k_init_fields<Lat, T><<<grid_1d(c->L.ps), 256, 0, c->stream>>>(
-      (T*)c->f[c->parity], c->links(), rho, u, c->L.ps, c->g.nx, c->g.ny, c->g.nz, c->L.xp,
-      c->g.rho0);
+  k_init_fields<Lat, T><<<grid_1d(n_nodes(c)), 256, 0, c->stream>>>(
+      (T*)c->f[c->parity], c->fmap(), rho, u, c->L.ps, c->g.rho0);
   HIP_TRY(hipGetLastError());
   return launch_bplane<Lat, T>(c);
 }
 
 template <class Lat, class T>
-lbm_status launch_flux(lbm_ctx* c) {
-  dim3 block(kTileX, kTileY);
-  k_flux<Lat, T><<<c->L.blocks, block, 0, c->stream>>>((const T*)c->f[c->parity], c->links(),
-                                                         c->partial(), c->L.ps, c->g.nx,
-                                                         c->g.ny, c->L.xp, c->L.tiles_x,
-                                                         c->L.tiles_y);
+lbm_status launch_flux(lbm_ctx* c, int* nparts) {
+  const unsigned nb = grid_1d(c->L.n_fluid ? c->L.n_fluid : 1);
+  k_flux<Lat, T><<<nb, 256, 0, c->stream>>>((const T*)c->f[c->parity], c->L.n_fluid, c->L.ps,
+                                              c->partial());
   HIP_TRY(hipGetLastError());
+  *nparts = (int)nb;
   return LBM_OK;
 }
 
 template <class Lat, class T>
 lbm_status launch_macro(lbm_ctx* c, void* rho, void* u, int dtype) {
-  const uint64_t N = (uint64_t)c->g.nx * c->g.ny * c->g.nz;
+  const unsigned nb = grid_1d(n_nodes(c));
   if (dtype == 0)
-    k_macro<Lat, T, float><<<grid_1d(N), 256, 0, c->stream>>>(
-        (const T*)c->f[c->parity], c->links(), (float*)rho, (float*)u, c->L.ps, c->g.nx,
-        c->g.ny, c->g.nz, c->L.xp, (T)c->g.rho0);
+    k_macro<Lat, T, float><<<nb, 256, 0, c->stream>>>((const T*)c->f[c->parity], c->fmap(),
+                                                       (float*)rho, (float*)u, c->L.ps,
+                                                       (T)c->g.rho0);
   else
-    k_macro<Lat, T, double><<<grid_1d(N), 256, 0, c->stream>>>(
-        (const T*)c->f[c->parity], c->links(), (double*)rho, (double*)u, c->L.ps, c->g.nx,
-        c->g.ny, c->g.nz, c->L.xp, (T)c->g.rho0);
+    k_macro<Lat, T, double><<<nb, 256, 0, c->stream>>>((const T*)c->f[c->parity], c->fmap(),
+                                                        (double*)rho, (double*)u, c->L.ps,
+                                                        (T)c->g.rho0);
   HIP_TRY(hipGetLastError());
   return LBM_OK;
 }
@@ -247,7 +277,7 @@ template <class Lat, class T> struct Fields {
   }
 };
 template <class Lat, class T> struct Flux {
-  static lbm_status run(lbm_ctx* c) { return launch_flux<Lat, T>(c); }
+  static lbm_status run(lbm_ctx* c, int* np) { return launch_flux<Lat, T>(c, np); }
 };
 template <class Lat, class T> struct Macro {
   static lbm_status run(lbm_ctx* c, void* r, void* u, int d) { return launch_macro<Lat, T>(c, r, u, d); }
@@ -256,9 +286,9 @@ template <class Lat, class T> struct Bplane {
   static lbm_status run(lbm_ctx* c) { return launch_bplane<Lat, T>(c); }
 };
 
-// Reduces the partials of the last flux pass into scalar[0] and reads it back.
-lbm_status reduce_flux(lbm_ctx* c, double* q) {
-  k_reduce<<<1, 256, 0, c->stream>>>(c->partial(), c->L.blocks, 1.0 / c->g.nx, c->scalar());
+// Reduces n partials of the last flux pass into scalar[0] and reads it back.
+lbm_status reduce_flux(lbm_ctx* c, int n, double* q) {
+  k_reduce<<<1, 1024, 0, c->stream>>>(c->partial(), n, 1.0 / c->g.nx, c->scalar());
   HIP_TRY(hipGetLastError());
   double h = 0.0;
   HIP_TRY(hipMemcpyAsync(&h, c->scalar(), sizeof(double), hipMemcpyDeviceToHost, c->stream));
@@ -268,9 +298,33 @@ lbm_status reduce_flux(lbm_ctx* c, double* q) {
 }
 
 lbm_status current_flux(lbm_ctx* c, double* q) {
-  lbm_status s = dispatch<Flux>(c);
+  int n = 0;
+  lbm_status s = dispatch<Flux>(c, &n);
   if (s != LBM_OK) return s;
-  return reduce_flux(c, q);
+  return reduce_flux(c, n, q);
+}
+
+// Bitmap, per-word prefix counts, and the fluid count check.
+lbm_status build_fluid_map(lbm_ctx* c) {
+  const Layout& L = c->L;
+  const uint64_t nwords = L.rows * L.nw;
+  k_pack_bits<<<(unsigned)((nwords * 64 + 255) / 256), 256, 0, c->stream>>>(
+      c->mask, c->bits(), c->count(), c->g.nx, c->g.ny, c->g.nz, L.nw);
+  HIP_TRY(hipGetLastError());
+  k_scan_local<<<L.scan_blocks, kScanBlock, 0, c->stream>>>(c->count(), c->pfx(), c->scan(), nwords);
+  HIP_TRY(hipGetLastError());
+  uint64_t* total = (uint64_t*)(c->scalar() + 1);
+  k_scan_totals<<<1, kScanBlock, 0, c->stream>>>(c->scan(), L.scan_blocks, total);
+  HIP_TRY(hipGetLastError());
+  k_scan_add<<<L.scan_blocks, kScanBlock, 0, c->stream>>>(c->pfx(), c->scan(), nwords);
+  HIP_TRY(hipGetLastError());
+  uint64_t h = 0;
+  HIP_TRY(hipMemcpyAsync(&h, total, sizeof h, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  if (h != L.n_fluid)
+    return fail(LBM_EINVAL, "the mask has %llu fluid nodes but geom.n_fluid is %llu",
+                (unsigned long long)h, (unsigned long long)L.n_fluid);
+  return LBM_OK;
 }
 
 double perm_from_flux(const lbm_ctx* c, double q) {
@@ -324,17 +378,14 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_geom* geom, const lbm_buffers* bufs
   c->parity = 0;
   c->steps = 0;
   c->linear_eq = 0;
+  c->xcd_remap = 1;
 
-  const uint64_t n_pad = L.ps;
   auto fail_free = [&](lbm_status st) { delete c; return st; };
-  if (geom->lattice == LBM_D2Q9)
-    k_links<D2Q9><<<grid_1d(n_pad), 256, 0, c->stream>>>(c->mask, c->links(), geom->nx, geom->ny,
-                                                          geom->nz, L.xp);
-  else
-    k_links<D3Q19><<<grid_1d(n_pad), 256, 0, c->stream>>>(c->mask, c->links(), geom->nx, geom->ny,
-                                                           geom->nz, L.xp);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return fail_free(fail(LBM_EHIP, "link kernel: %s", hipGetErrorString(e)));
+  s = build_fluid_map(c);
+  if (s != LBM_OK) return fail_free(s);
+  hipError_t e = hipMemsetAsync(c->f[0], 0, L.f_bytes, c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(c->f[1], 0, L.f_bytes, c->stream);
+  if (e != hipSuccess) return fail_free(fail(LBM_EHIP, "hipMemsetAsync: %s", hipGetErrorString(e)));
   s = dispatch<Reset>(c, (int)LBM_START_UNIFORM);
   if (s != LBM_OK) return fail_free(s);
   *out = c;
@@ -409,7 +460,7 @@ lbm_status lbm_run_to_steady(lbm_ctx* c, double tol, int64_t max_steps, int64_t*
     s = dispatch<Steps>(c, (int64_t)K, true);
     if (s != LBM_OK) return s;
     double q;
-    s = reduce_flux(c, &q);
+    s = reduce_flux(c, c->L.blocks, &q);
     if (s != LBM_OK) return s;
     if (!isfinite(q)) {
       if (steps_out) *steps_out = c->steps;
@@ -448,6 +499,22 @@ lbm_status lbm_set_populations(lbm_ctx* c, const void* src) {
   HIP_TRY(hipMemcpyAsync(c->f[c->parity], src, c->L.f_bytes, hipMemcpyDeviceToDevice, c->stream));
   lbm_status s = dispatch<Bplane>(c);
   return s == LBM_OK ? ok() : s;
+}
+
+lbm_status lbm_set_option(lbm_ctx* c, int32_t option, int64_t value) {
+  if (!c) return fail(LBM_EINVAL, "ctx is NULL");
+  switch (option) {
+    case LBM_OPT_XCD_REMAP:
+      if (value != 0 && value != 1) return fail(LBM_EINVAL, "XCD remap is 0 or 1");
+      c->xcd_remap = (int)value;
+      return ok();
+    case LBM_OPT_LINEAR_EQ:
+      if (value != 0 && value != 1) return fail(LBM_EINVAL, "linear equilibrium is 0 or 1");
+      c->linear_eq = (int)value;
+      return ok();
+    default:
+      return fail(LBM_EINVAL, "unknown option %d", option);
+  }
 }
 
 lbm_status lbm_lattice(int32_t lattice, int32_t* cv, double* w) {

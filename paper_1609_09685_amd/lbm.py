@@ -30,7 +30,8 @@ class LBMError(RuntimeError):
 class Geom(ctypes.Structure):
     _fields_ = [("lattice", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
                 ("nz", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("check_every", ctypes.c_int32), ("rho0", ctypes.c_double)]
+                ("check_every", ctypes.c_int32), ("rho0", ctypes.c_double),
+                ("n_fluid", ctypes.c_int64)]
 
 
 class Buffers(ctypes.Structure):
@@ -56,6 +57,7 @@ _SIGS = {
     "lbm_get_macro": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_int32]),
     "lbm_get_populations": (_c.c_int, [_c.c_void_p, _c.c_void_p]),
     "lbm_set_populations": (_c.c_int, [_c.c_void_p, _c.c_void_p]),
+    "lbm_set_option": (_c.c_int, [_c.c_void_p, _c.c_int32, _c.c_int64]),
     "lbm_lattice": (_c.c_int, [_c.c_int32, _c.c_void_p, _c.c_void_p]),
     "lbm_steps": (_c.c_int, [_c.c_void_p, _c.POINTER(_c.c_int64)]),
     "lbm_knudsen": (_c.c_double, [_c.c_double, _c.c_int32]),
@@ -94,8 +96,11 @@ def _check(status, allow=()):
     return status
 
 
-def query_sizes(lattice, nx, ny, nz, precision="fp32", check_every=100, rho0=1.0):
-    g = Geom(lattice, nx, ny, nz, _PRECISION[precision], check_every, rho0)
+LBM_OPT_XCD_REMAP, LBM_OPT_LINEAR_EQ = 1, 2
+
+
+def query_sizes(lattice, nx, ny, nz, n_fluid, precision="fp32", check_every=100, rho0=1.0):
+    g = Geom(lattice, nx, ny, nz, _PRECISION[precision], check_every, rho0, n_fluid)
     fb, wb = ctypes.c_size_t(0), ctypes.c_size_t(0)
     _check(load_library().lbm_query_sizes(ctypes.byref(g), ctypes.byref(fb), ctypes.byref(wb)))
     return fb.value, wb.value
@@ -141,8 +146,9 @@ class Solver:
         self.tau, self.rho_in, self.rho_out = float(tau), float(rho_in), float(rho_out)
         self.D = 2 if self.lattice == LBM_D2Q9 else 3
         self.device = torch.device(device)
+        self.n_fluid = int((m == 0).sum())
         self._geom = Geom(self.lattice, self.nx, self.ny, self.nz, _PRECISION[precision],
-                          int(check_every), float(rho0))
+                          int(check_every), float(rho0), self.n_fluid)
         fb, wb = ctypes.c_size_t(0), ctypes.c_size_t(0)
         _check(lib.lbm_query_sizes(ctypes.byref(self._geom), ctypes.byref(fb), ctypes.byref(wb)))
         self.f_bytes, self.work_bytes = fb.value, wb.value
@@ -170,6 +176,15 @@ class Solver:
             self._h = None
 
     __del__ = close
+
+    def set_option(self, option, value):
+        _check(self._lib.lbm_set_option(self._h, int(option), int(value)))
+
+    def set_linear_equilibrium(self, on=True):
+        self.set_option(LBM_OPT_LINEAR_EQ, 1 if on else 0)
+
+    def set_xcd_remap(self, on=True):
+        self.set_option(LBM_OPT_XCD_REMAP, 1 if on else 0)
 
     # -- state --------------------------------------------------------------
     def reset(self, start="uniform"):

@@ -18,16 +18,39 @@ def direction_map(Q):
     return np.array([lookup[tuple(v)] for v in c_or])
 
 
-def state_view(solver, buf=None):
-    """The solver's current populations as a device tensor (Q, nz, ny, xp)."""
+def _dtype(solver):
     import torch
+    return torch.float64 if solver.precision == "fp64" else torch.float32
+
+
+def compact_view(solver, buf=None):
+    """The solver's populations as a device tensor (Q, ps): direction-major,
+    fluid nodes only, x-fastest order, padded to ps entries."""
     if buf is None:
         buf = solver.get_populations()
-    dt = torch.float64 if solver.precision == "fp64" else torch.float32
-    es = 8 if solver.precision == "fp64" else 4
     Q = solver.lattice
-    xp = solver.f_bytes // (Q * solver.nz * solver.ny * es)
-    return buf.view(dt).view(Q, solver.nz, solver.ny, xp)
+    return buf.view(_dtype(solver)).view(Q, -1)
+
+
+def fluid_index(solver):
+    """Dense flat indices (x fastest) of the fluid nodes, in compact order."""
+    import torch
+    m = solver._mask.view(-1)
+    return torch.nonzero(m == 0, as_tuple=False).view(-1)
+
+
+def dense_state(solver, buf=None):
+    """(Q, nz, ny, nx) device tensor of the deviations, 0 on solids."""
+    import torch
+    c = compact_view(solver, buf)
+    Q = solver.lattice
+    n = solver.nx * solver.ny * solver.nz
+    out = torch.zeros((Q, n), dtype=c.dtype, device=c.device)
+    out[:, fluid_index(solver)] = c[:, : solver.n_fluid]
+    return out.view(Q, solver.nz, solver.ny, solver.nx)
+
+
+state_view = dense_state
 
 
 def to_oracle_f(g_window, Q, rho0=1.0):
@@ -51,25 +74,21 @@ def from_oracle_f(f, Q, shape, rho0=1.0):
 
 
 def random_state(solver, scale=1e-4, seed=0):
-    """Seeded random deviations g_i = w_i * scale * N(0,1) on fluid nodes (0 on
-    solids and padding), written into the solver's current state."""
+    """Seeded random deviations g_i = w_i * scale * N(0,1) on every fluid node,
+    written into the solver's current state; returns the dense (Q, nz, ny, nx)
+    view of what was written (0 on solids)."""
     import torch
     Q = solver.lattice
-    v = state_view(solver)
-    gen = torch.Generator(device=v.device)
+    buf = torch.empty(solver.f_bytes, dtype=torch.uint8, device=solver.device)
+    c = compact_view(solver, buf)
+    gen = torch.Generator(device=c.device)
     gen.manual_seed(seed)
     _, w = lbm.lattice_table(Q)
-    wt = torch.tensor(w, dtype=v.dtype, device=v.device).view(Q, 1, 1, 1)
-    buf = torch.empty(solver.f_bytes, dtype=torch.uint8, device=v.device)
-    state = buf.view(v.dtype).view(v.shape)
-    state.normal_(generator=gen)
-    state.mul_(wt * scale)
-    m = torch.from_numpy(solver_mask(solver)).to(v.device)
-    fluid = torch.zeros(v.shape[1:], dtype=torch.bool, device=v.device)
-    fluid[:, :, : solver.nx] = m == 0
-    state.masked_fill_(~fluid[None], 0)
+    c.normal_(generator=gen)
+    c.mul_(torch.tensor(w, dtype=c.dtype, device=c.device).view(Q, 1) * scale)
+    c[:, solver.n_fluid:] = 0
     solver.set_populations(buf)
-    return state
+    return dense_state(solver, buf)
 
 
 def solver_mask(solver):

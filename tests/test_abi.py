@@ -48,6 +48,7 @@ def test_binding_covers_header():
 def _geom(**kw):
     d = dict(lattice=9, nx=100, ny=50, nz=1, precision=lbm.LBM_FP64, check_every=100, rho0=1.0)
     d.update(kw)
+    d.setdefault("n_fluid", d["nx"] * d["ny"] * d["nz"])
     return lbm.Geom(**d)
 
 
@@ -59,22 +60,26 @@ def _status(g):
 
 @pytest.mark.parametrize("kw", [dict(lattice=7), dict(nz=2), dict(nx=1), dict(ny=0),
                                 dict(precision=5), dict(check_every=0), dict(rho0=0.0),
-                                dict(rho0=float("nan")),
-                                dict(lattice=19, nx=2048, ny=2048, nz=1024)])
+                                dict(rho0=float("nan")), dict(n_fluid=-1),
+                                dict(n_fluid=100 * 50 + 1),
+                                dict(lattice=19, nx=2048, ny=2048, nz=1025, n_fluid=2**32 + 5)])
 def test_query_sizes_rejects(kw):
     st, _, _ = _status(_geom(**kw))
     assert st == lbm.LBM_EINVAL
     assert lbm.load_library().lbm_last_error()
 
 
-@pytest.mark.parametrize("lat,prec,nx,ny,nz,esize,pitch", [
-    (9, lbm.LBM_FP64, 100, 50, 1, 8, 112), (9, lbm.LBM_FP32, 100, 50, 1, 4, 128),
-    (19, lbm.LBM_FP32, 512, 512, 512, 4, 512), (19, lbm.LBM_FP64, 33, 7, 5, 8, 48)])
-def test_query_sizes_layout(lat, prec, nx, ny, nz, esize, pitch):
-    st, fb, wb = _status(_geom(lattice=lat, precision=prec, nx=nx, ny=ny, nz=nz))
+@pytest.mark.parametrize("lat,prec,nx,ny,nz,nf,esize", [
+    (9, lbm.LBM_FP64, 100, 50, 1, 3700, 8), (9, lbm.LBM_FP32, 100, 50, 1, 3700, 4),
+    (19, lbm.LBM_FP32, 512, 512, 512, 80530637, 4), (19, lbm.LBM_FP64, 33, 7, 5, 1, 8),
+    (9, lbm.LBM_FP32, 7, 3, 1, 0, 4)])
+def test_query_sizes_layout(lat, prec, nx, ny, nz, nf, esize):
+    st, fb, wb = _status(_geom(lattice=lat, precision=prec, nx=nx, ny=ny, nz=nz, n_fluid=nf))
     assert st == lbm.LBM_OK
-    assert fb == lat * nz * ny * pitch * esize          # SoA, x pitch padded to 128 B
-    assert wb >= nz * ny * pitch * 4                    # one link word per padded node
+    ps = max(64, (nf + 63) // 64 * 64)              # fluid nodes only, padded to 64
+    assert fb == lat * ps * esize
+    nw = (nx + 63) // 64
+    assert wb >= ny * nz * (nw + 2) * 8 + ny * nz * nw * 4   # bitmap + prefix counts
 
 
 def test_init_validates_before_any_hip_call():

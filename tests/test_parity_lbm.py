@@ -13,8 +13,8 @@ import oracle
 from paper_1609_09685_amd import lbm
 from paper_1609_09685_amd.qsgs import qsgs_2d, qsgs_3d
 
-from lbm_testutil import (field_floor, fields_match, from_oracle_f, random_state, state_view,
-                          to_oracle_f)
+from lbm_testutil import (compact_view, field_floor, fields_match, from_oracle_f, random_state,
+                          state_view, to_oracle_f)
 
 pytestmark = pytest.mark.gpu
 
@@ -105,12 +105,11 @@ def test_edge_shapes_random_state(Q, shape, precision):
         mask.reshape(-1)[0] = 0
     s, o = _pair(Q, mask, precision, 0.7, 1.002, 0.998)
     g0 = random_state(s, scale=1e-3, seed=1).cpu().numpy()
-    nx = mask.shape[-1]
-    o.set_f(to_oracle_f(g0[..., :nx], Q))
+    o.set_f(to_oracle_f(g0, Q))
     for n in (1, 5):
         s.step(n)
         o.step(n)
-        g = state_view(s).cpu().numpy()[..., :nx].astype(np.float64)
+        g = state_view(s).cpu().numpy().astype(np.float64)
         go = from_oracle_f(o.get_f(), Q, mask.reshape((1,) * (3 - mask.ndim) + mask.shape).shape)
         fl = ~mask.reshape(go.shape[1:]).astype(bool)
         err = np.abs(g[:, fl] - go[:, fl]).max()
@@ -124,7 +123,7 @@ def test_rest_state_bitwise(Q):
     m = qsgs_2d(100, 50, 0.74, 1) if Q == 9 else qsgs_3d(40, 24, 20, 0.6, 1)
     s = lbm.Solver(m, 0.8, 1.0, 1.0, precision="fp32")
     s.step(1000)
-    v = state_view(s)
+    v = compact_view(s)
     assert int((v != 0).sum()) == 0
 
 
@@ -210,6 +209,38 @@ def test_no_flow_and_nonfinite():
     with pytest.raises(lbm.LBMError) as e:
         s.run_to_steady(1e-9, 1000)
     assert e.value.status == lbm.LBM_ENONFINITE
+
+
+def test_fluid_count_checked_at_init(c1_mask):
+    import ctypes
+    import torch
+    lib = lbm.load_library()
+    nf = int((c1_mask == 0).sum())
+    g = lbm.Geom(9, 100, 50, 1, lbm.LBM_FP32, 100, 1.0, nf + 1)
+    fb, wb = lbm.query_sizes(9, 100, 50, 1, nf + 1)
+    f0 = torch.empty(fb, dtype=torch.uint8, device="cuda")
+    f1 = torch.empty(fb, dtype=torch.uint8, device="cuda")
+    wk = torch.empty(wb, dtype=torch.uint8, device="cuda")
+    mk = torch.from_numpy(c1_mask.reshape(-1).copy()).cuda()
+    b = lbm.Buffers()
+    b.f[0], b.f[1], b.mask, b.work = f0.data_ptr(), f1.data_ptr(), mk.data_ptr(), wk.data_ptr()
+    b.stream = torch.cuda.current_stream().cuda_stream
+    h = ctypes.c_void_p(0)
+    st = lib.lbm_init(ctypes.byref(h), ctypes.byref(g), ctypes.byref(b), 0.8, 1.0005, 0.9995)
+    assert st == lbm.LBM_EINVAL and b"fluid" in lib.lbm_last_error()
+    assert not h.value
+
+
+@pytest.mark.parametrize("remap", [0, 1])
+def test_xcd_remap_is_bitwise_neutral(c1_mask, remap):
+    a = lbm.Solver(c1_mask, **C1, precision="fp32")
+    b = lbm.Solver(c1_mask, **C1, precision="fp32")
+    b.set_xcd_remap(bool(remap))
+    a.set_xcd_remap(not remap)
+    a.step(300)
+    b.step(300)
+    assert bool((a.get_populations() == b.get_populations()).all())
+    assert a.flux() == b.flux()
 
 
 def test_not_converged_status(c1_mask):
