@@ -69,6 +69,30 @@ def cpu_baseline(Q, mask, tau, rho_in, rho_out, budget_s=12.0):
                       f"({dt:.1f} s wall)"}
 
 
+def copy_ceiling(gib=4, reps=5):
+    """A plain device-to-device copy of `gib` GiB (torch's copy kernel), timed
+    with HIP events: the achievable streaming bandwidth on this GPU, and the
+    reference kernel of known size for scaling the HBM byte counters."""
+    import torch
+    n = gib * (1 << 30) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    moved = 2 * n * 4
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"bytes_per_copy": moved, "ms": round(ms, 4), "gbs": round(moved / (ms / 1e3) / 1e9, 1)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -76,7 +100,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="d3q19_512_fp32", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--xcd-remap", type=int, default=1, choices=[0, 1])
+    ap.add_argument("--xcd-remap", type=int, default=1)
+    ap.add_argument("--band", type=int, default=16, help="banded tile order (tile rows per band; 0: off)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU runs are not "
@@ -92,7 +117,7 @@ def main():
     log(f"mask {shape} porosity {1 - mask.mean():.4f} in {time.time() - t0:.1f} s")
     torch.cuda.set_device(0)
     s = lbm.Solver(mask, tau, rin, rout, precision=prec, lattice=Q)
-    s.set_xcd_remap(bool(args.xcd_remap))
+    s.configure(xcd_remap=args.xcd_remap, band=args.band)
     N = int(mask.size)
     n_fluid = int((mask == 0).sum())
     esize = 8 if prec == "fp64" else 4
@@ -135,6 +160,8 @@ def main():
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                      "kernel": "k_step", "algorithmic_bytes_per_launch": alg_bytes},
     }
+    out["copy_ceiling"] = copy_ceiling()
+    log(f"plain copy: {out['copy_ceiling']['gbs']:.0f} GB/s")
     if not args.no_cpu_baseline:
         log("cpu baseline ...")
         out["cpu_baseline"] = cpu_baseline(Q, mask, tau, rin, rout)

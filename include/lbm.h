@@ -41,9 +41,11 @@
  *
  * Storage: populations are kept for fluid nodes only, as deviations from the
  * rest state, g_i = f_i - w_i rho0 (so that the tiny Stokes-regime pressure
- * differences survive FP32 rounding), direction-major: g[i][k] where k numbers
- * the fluid nodes in x-fastest order (x, then y, then z) and each direction's
- * array holds n_fluid rounded up to a multiple of 64 entries.  The solid mask
+ * differences survive FP32 rounding), direction-major: g[i][k] where k is the
+ * node's slot.  Slots follow the fluid nodes in x-fastest order (x, then y,
+ * then z); each row is cut into segments of up to 256 nodes along x, and every
+ * segment starts on a 128-byte boundary, the slots between two segments being
+ * zero padding.  lbm_get_slot_map gives the slot of every node.  The solid mask
  * is uint8, [nz][ny][nx] with x fastest, 1 = solid, 0 = fluid.
  */
 #ifndef LBM_H_
@@ -71,8 +73,13 @@ enum { LBM_D2Q9 = 9, LBM_D3Q19 = 19 };
 enum { LBM_FP64 = 0, LBM_FP32 = 1 };          /* storage and in-kernel arithmetic */
 enum { LBM_START_UNIFORM = 0, LBM_START_LINEAR = 1 };
 enum {
-  LBM_OPT_XCD_REMAP = 1,  /* 1 (default): deal consecutive tiles to one XCD; 0: hardware order */
-  LBM_OPT_LINEAR_EQ = 2   /* 1: equilibrium without the terms quadratic in u (Stokes); 0 (default) */
+  LBM_OPT_XCD_REMAP = 1,  /* tile order over the 8 XCDs when LBM_OPT_BAND is 0: 0 hardware
+                             order; 1 one contiguous eighth per XCD (default); m >= 2 chunks
+                             of m - 1 tile rows dealt round-robin */
+  LBM_OPT_LINEAR_EQ = 2,  /* 1: equilibrium without the terms quadratic in u (Stokes); 0 (default) */
+  LBM_OPT_BAND = 6        /* > 0: banded tile order: bands of this many tile rows, one band
+                             per XCD at a time, each walked plane by plane (overrides
+                             LBM_OPT_XCD_REMAP); default 16; 0: off */
 };
 
 typedef struct lbm_ctx lbm_ctx;               /* opaque; host metadata only */
@@ -143,10 +150,15 @@ lbm_status lbm_run_to_steady(lbm_ctx *ctx, double tol, int64_t max_steps,
 lbm_status lbm_get_macro(lbm_ctx *ctx, void *rho, void *u, int32_t dtype);
 
 /* Checkpoint / restore: copies the current population buffer (f_bytes, the
- * compact layout above, in the direction order of lbm_lattice) to / from
- * device memory.  lbm_set_populations keeps the step count. */
+ * slot layout above, in the direction order of lbm_lattice) to / from device
+ * memory.  Padding and unused slots must hold zero (as lbm_get_populations
+ * returns them).  lbm_set_populations keeps the step count. */
 lbm_status lbm_get_populations(lbm_ctx *ctx, void *dst);
 lbm_status lbm_set_populations(lbm_ctx *ctx, const void *src);
+
+/* Slot of every node in the population arrays into a caller device buffer:
+ * int32 [nz][ny][nx], -1 for solid nodes. */
+lbm_status lbm_get_slot_map(lbm_ctx *ctx, int32_t *map);
 
 /* Tuning and model options (LBM_OPT_*); take effect at the next step. */
 lbm_status lbm_set_option(lbm_ctx *ctx, int32_t option, int64_t value);

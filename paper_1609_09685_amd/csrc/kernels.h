@@ -12,9 +12,15 @@
 // fluid inside almost every 128-byte line, so a dense array would drag the
 // solid slots through HBM with the fluid ones.  Populations are therefore kept
 // for fluid nodes only, numbered in x-fastest (x, y, z) order:
-//     g[i][k],  i = direction, k = compact fluid index,
-// as deviations from the rest state, g_i = f_i - w_i rho0.  Each direction's
-// array is padded to 64 entries.
+//     g[i][k],  i = direction, k = slot of the fluid node,
+// as deviations from the rest state, g_i = f_i - w_i rho0.  Each row is cut
+// into segments of S = seg bitmap words (S x 64 nodes); a segment's slots start
+// on a 128-byte boundary and the slots between its last fluid node and the
+// next boundary are padding (always zero).  A block of the step kernel covers
+// one segment of each of 4 / S rows, gathers its outputs in LDS and writes
+// every segment as whole aligned lines: a wavefront storing its own scattered
+// fluid lanes would leave partial lines that the memory system writes at a
+// fraction of the bandwidth.
 //
 // The pull source of a node is found from a bitmap of the mask: for every
 // (y, z) row, 64-bit words with bit x%64 set for fluid nodes (one guard word
@@ -69,7 +75,8 @@ __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirs
 
 // Bitmap of the fluid nodes.  bits: [nz][ny][nw + 2] words, word w + 1 holds
 // x in [64 w, 64 w + 64), words 0 and nw + 1 are zero guards.  pfx: [nz][ny][nw],
-// compact index of the first fluid node at or after x = 64 w of that row.
+// slot of the first fluid node at or after x = 64 w of that row (fluid nodes of
+// one segment have consecutive slots).
 struct FluidMap {
   const uint64_t* __restrict__ bits;
   const uint32_t* __restrict__ pfx;
@@ -88,19 +95,42 @@ struct FluidMap {
   }
 };
 
+// Division by a divisor fixed at launch, for 0 <= n < 2^31: q = (mulhi(n, m) +
+// n) >> l with l = ceil(log2 d) and m = 2^32 (2^l - d) / d + 1 (round-up
+// multiplier; Granlund & Montgomery 1994).  Replaces the scalar division
+// sequences of the tile decode.
+struct FastDiv {
+  uint32_t d, m, l;
+  __host__ __device__ __forceinline__ uint32_t div(uint32_t n) const {
+    return (__umulhi(n, m) + n) >> l;
+  }
+};
+
 // Arguments of one domain's step.
 template <class T>
 struct StepArgs {
-  const T* __restrict__ src;       // populations of step t
+  const T* __restrict__ src;       // populations of step t: direction i at src + i * ps
   T* __restrict__ dst;             // populations of step t+1
-  FluidMap fm;
+  const T* src_g1;                 // src + group_split * ps (second direction group)
+  T* dst_g1;
+  uint32_t ps_bytes;               // ps * sizeof(T) (32-bit offset kernels)
+  const uint64_t* __restrict__ bits;   // fluid bitmap, guard-padded rows (FluidMap)
+  const uint32_t* __restrict__ pfx;
   const T* __restrict__ bp_src;    // edge-node moments of step t: [2 sides][D+1][nz*ny]
   T* __restrict__ bp_dst;          // edge-node moments written by this step
-  double* __restrict__ partial;    // per-block flux partials (flux variant)
+  double* __restrict__ partial;    // per-word flux partials (flux variant)
   uint64_t ps;                     // elements between two direction arrays
-  int tiles_y;                     // ceil(ny / kRows)
-  int blocks;                      // nw * tiles_y * nz
-  int xcd_remap;                   // 1: consecutive tiles on the same XCD
+  int nx, ny, nz, nw;              // lattice; nw = bitmap words per row
+  int seg;                         // S: words (64 x) per segment and tile: 1, 2 or 4
+  int tiles_x, tiles_y;            // ceil(nw / S), ceil(ny / (4 / S))
+  uint32_t align;                  // slots per 128 bytes
+  int blocks;                      // tiles_x * tiles_y * nz
+  int xcd_remap;                   // tile order mode (see logical_block)
+  int chunk;                       // tiles per chunk in mode >= 2
+  int band;                        // > 0: banded order, band = tile rows per band
+  int nbands;                      // ceil(tiles_y / band)
+  FastDiv dv_tiles_x, dv_tiles_y, dv_chunk;
+  FastDiv dv_band_blocks, dv_band_plane;   // nz * band * tiles_x, band * tiles_x
   T omega, rho0, drho_in, drho_out;  // 1/tau; rho0; rho_in - rho0; rho_out - rho0
 };
 
@@ -129,23 +159,51 @@ __device__ __forceinline__ void block_sum_store(double v, double* out) {
   }
 }
 
-// Deterministic second pass: one block sums n partials, out = scale * sum.
-__global__ __launch_bounds__(1024) void k_reduce(const double* __restrict__ partial, int n,
-                                                 double scale, double* __restrict__ out) {
-  double v = 0.0;
-  for (int i = threadIdx.x; i < n; i += 1024) v += partial[i];
+// Deterministic reduction of n partials in two passes with a fixed chunking
+// (independent of how the partials were produced): pass 1 sums chunk c =
+// [c * kChunk, (c + 1) * kChunk) in a fixed order into chunk[c]; pass 2 sums the
+// chunks in a fixed order, out = scale * total.
+constexpr int kChunk = 8192;
+
+__device__ __forceinline__ double block1024_sum(double v) {
   __shared__ double s[16];
   v = wave_sum(v);
   if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = v;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    double t = 0.0;
+  double t = 0.0;
+  if (threadIdx.x == 0)
     for (int i = 0; i < 16; ++i) t += s[i];
-    out[0] = scale * t;
-  }
+  return t;   // valid in thread 0
+}
+
+__global__ __launch_bounds__(1024) void k_reduce_chunks(const double* __restrict__ partial, int n,
+                                                        double* __restrict__ chunk) {
+  const int base = blockIdx.x * kChunk;
+  double v = 0.0;
+  for (int j = threadIdx.x; j < kChunk; j += 1024)
+    if (base + j < n) v += partial[base + j];
+  const double t = block1024_sum(v);
+  if (threadIdx.x == 0) chunk[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(1024) void k_reduce_final(const double* __restrict__ chunk, int nchunks,
+                                                       double scale, double* __restrict__ out) {
+  double v = 0.0;
+  for (int i = threadIdx.x; i < nchunks; i += 1024) v += chunk[i];
+  const double t = block1024_sum(v);
+  if (threadIdx.x == 0) out[0] = scale * t;
 }
 
 // -------------------------------------------------------------- equilibrium
+
+// 1 / rho for the velocity.  FP32: the hardware reciprocal (1 ulp); FP64: a
+// correctly rounded division.
+template <class T>
+__device__ __forceinline__ T recip(T v) {
+  if constexpr (std::is_same<T, float>::value) return __builtin_amdgcn_rcpf(v);
+  return T(1) / v;
+}
+
 
 template <class L, int q, class T>
 __device__ __forceinline__ T dot_c(T ux, T uy, T uz) {
@@ -185,7 +243,7 @@ __device__ __forceinline__ void stored_moments(Get get, T rho0, T& drho, T& ux, 
     if constexpr (L::cz[q] == 1) jz += v;
     if constexpr (L::cz[q] == -1) jz -= v;
   });
-  const T inv = T(1) / (rho0 + d);
+  const T inv = recip(rho0 + d);
   drho = d;
   ux = jx * inv;
   uy = jy * inv;
@@ -196,7 +254,7 @@ __device__ __forceinline__ void stored_moments(Get get, T rho0, T& drho, T& ux, 
 
 // Non-equilibrium extrapolation term of a ghost population (rule 3).
 template <class L, bool LINEAR, class T>
-__device__ __noinline__ T ghost_term(const T* __restrict__ bp, int side, uint32_t plane,
+__device__ __forceinline__ T ghost_term(const T* __restrict__ bp, int side, uint32_t plane,
                                      uint32_t at, T drho_set, T wq, int cxk, int cyk, int czk) {
   const T* p = bp + (size_t)side * (L::D + 1) * plane + at;
   const T drb = p[0];
@@ -208,97 +266,170 @@ __device__ __noinline__ T ghost_term(const T* __restrict__ bp, int side, uint32_
   return wq * (drho_set - drb) * P;
 }
 
-// The bitmap of one source row around the wave's word, reduced to what a lane
-// needs: its rank in the row (r0 = fluid nodes of the row before x) and the
-// fluid bits of x-1, x, x+1 in that row.
-struct RowView {
-  uint32_t r0;
-  uint32_t fm, f0, fp;   // fluid(x-1), fluid(x), fluid(x+1)
-};
-
-__device__ __forceinline__ RowView row_view(const FluidMap& fm, int y, int z, int w, int p) {
-  const uint64_t* wd = fm.words(y, z) + w;   // uniform address: scalar loads
-  const uint64_t lo = wd[-1], mid = wd[0], hi = wd[1];
-  const uint32_t base = fm.pfx[fm.row(y, z) * fm.nw + w];
-  const uint64_t below = (1ull << p) - 1ull;
-  const uint64_t sh_lo = (mid << 1) | (lo >> 63);   // bit p = fluid(x-1)
-  const uint64_t sh_hi = (mid >> 1) | (hi << 63);   // bit p = fluid(x+1)
-  RowView r;
-  r.r0 = base + (uint32_t)__popcll(mid & below);
-  r.f0 = (uint32_t)(mid >> p) & 1u;
-  r.fm = (uint32_t)(sh_lo >> p) & 1u;
-  r.fp = (uint32_t)(sh_hi >> p) & 1u;
-  return r;
+// Bit `lane` of a wave-uniform 64-bit mask.
+__device__ __forceinline__ uint32_t lane_bit(uint64_t m, int lane) {
+  return (uint32_t)(m >> lane) & 1u;
 }
 
-// Updates one node of a wave covering x = 64 w + p of row (y, z) (y, z, w
-// uniform across the wave).  Returns the node's x-momentum (0 if not fluid).
-template <class L, class T, bool LINEAR>
-__device__ __forceinline__ T node_update(const StepArgs<T>& a, int y, int z, int w, int p) {
-  const FluidMap& fm = a.fm;
-  const int x = (w << 6) + p;
-  // mirror planes act on whole rows: the row choice is uniform per wave
-  const bool y0 = y == 0, y1 = y == fm.ny - 1;
-  const bool z0 = z == 0, z1 = z == fm.nz - 1;
-  RowView rv[3][3];   // [dz + 1][dy + 1]: source row (y + dy, z + dz), mirrored
+// Bit `lane` of a wave-uniform 64-bit mask as 0 or ~0u: a 64-bit shift by the
+// lane id and a signed one-bit field extract.
+__device__ __forceinline__ uint32_t lane_mask(uint64_t m, int lane) {
+  return (uint32_t)__builtin_amdgcn_sbfe((int)(uint32_t)(m >> lane), 0u, 1u);
+}
+
+// (a & m) | (b & ~m): a where m is all ones, b where it is zero.
+__device__ __forceinline__ uint32_t pick(uint32_t m, uint32_t a, uint32_t b) {
+  return (a & m) | (b & ~m);
+}
+
+// pfx + popcount(m & ((1 << lane) - 1)): the compact index of the lane's node
+// when m is the fluid word of its row (two mbcnt instructions).
+__device__ __forceinline__ uint32_t lane_rank(uint64_t m, uint32_t pfx) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, pfx));
+}
+
+// The bitmap of one source row around the wave's word: words w-1, w, w+1, the
+// slot of the first fluid node of word w (base), the slot after the last fluid
+// node of word w-1 (end_lo) and the slot of the first fluid node of word w+1
+// (base_hi), all wave-uniform.  Slots run on within a segment, but a segment
+// boundary between two words leaves a padding gap, so the neighbours of lanes
+// 0 and 63 are numbered from their own words.
+struct RowWords {
+  uint64_t lo, mid, hi;
+  uint32_t base, end_lo, base_hi;
+};
+
+// Updates the node x = 64 w + lane of row (y, z); y, z, w are uniform across
+// the wave.  YZE: the row touches a symmetric plane (mirrors possible); XE: the
+// word holds x = 0 or x = nx - 1 (ghost planes possible).  Interior waves
+// (neither) skip all boundary logic.  OFF32: each direction group spans less
+// than 4 GiB, so loads and stores use a uniform group base plus a 32-bit lane
+// offset.  The post-collision populations go to out[i][lds_base + slot] (LDS;
+// lds_base = the block-local position of the segment minus its first slot).
+// Returns the node's x-momentum (0 if the node is not fluid).
+template <class L, class T, bool LINEAR, bool OFF32, bool YZE, bool XE>
+__device__ __forceinline__ T node_update(const StepArgs<T>& a, int y, int z, int w, int lane,
+                                         T (*out)[kThreads], uint32_t lds_base) {
+  const int x = (w << 6) + lane;
+  const bool y0 = YZE && y == 0, y1 = YZE && y == a.ny - 1;
+  const bool z0 = YZE && L::D == 3 && z == 0, z1 = YZE && L::D == 3 && z == a.nz - 1;
+  const uint32_t row_self = (uint32_t)z * (uint32_t)a.ny + (uint32_t)y;
+  const uint32_t wi_self = row_self * (uint32_t)(a.nw + 2) + 1u + (uint32_t)w;
+  const uint32_t pi_self = row_self * (uint32_t)a.nw + (uint32_t)w;
+
+  // source rows (y + dy, z + dz), mirrored onto the own row at a symmetric plane
+  RowWords rw[3][3];
   unroll<0, 3>([&](auto izc) {
     constexpr int dz = decltype(izc)::value - 1;
     if constexpr (L::D == 3 || dz == 0) {
       unroll<0, 3>([&](auto iyc) {
         constexpr int dy = decltype(iyc)::value - 1;
-        const int yy = (dy < 0 && y0) || (dy > 0 && y1) ? y : y + dy;
-        const int zz = (dz < 0 && z0) || (dz > 0 && z1) ? z : z + dz;
-        rv[dz + 1][dy + 1] = row_view(fm, yy, zz, w, p);
+        int ey = dy, ez = dz;
+        if constexpr (YZE) {
+          if ((dy < 0 && y0) || (dy > 0 && y1)) ey = 0;
+          if ((dz < 0 && z0) || (dz > 0 && z1)) ez = 0;
+        }
+        const int drow = ez * a.ny + ey;
+        const uint64_t* wp = a.bits + (wi_self + (uint32_t)(drow * (a.nw + 2)));
+        const uint32_t* pp = a.pfx + (pi_self + (uint32_t)(drow * a.nw));
+        RowWords& r = rw[dz + 1][dy + 1];
+        r.lo = wp[-1];
+        r.mid = wp[0];
+        r.hi = wp[1];
+        r.base = pp[0];
+        // neighbour words' slots; at a row end the value is unused (ghost lanes)
+        r.end_lo = (w > 0 ? pp[-1] : pp[0]) + (uint32_t)__popcll(r.lo);
+        r.base_hi = w + 1 < a.nw ? pp[1] : pp[0];
       });
     }
   });
-  const RowView& me = rv[1][1];
-  if (!me.f0) return T(0);   // solid node, or x >= nx
-  const uint32_t self = me.r0;
-  const bool x0 = x == 0, x1 = x == fm.nx - 1;
+  const RowWords& me = rw[1][1];
+  if (!lane_bit(me.mid, lane)) return T(0);   // solid node, or x >= nx
+  const uint32_t self = lane_rank(me.mid, me.base);
+  const bool x0 = XE && x == 0, x1 = XE && x == a.nx - 1;
 
+  // Gather: for every direction, whether the (mirrored) source is fluid and
+  // its compact index; a solid source reads the node's own slot of the
+  // opposite direction (halfway bounce-back).  Ghost sources (x-edge lanes)
+  // use the edge node b.  Both candidate addresses lie in the same direction
+  // group, so one load with a selected offset serves both.
+  const uint32_t selfb = self * (uint32_t)sizeof(T);
   T g[L::Q];
+  uint32_t ghm[L::Q];   // ~0u: fluid ghost source (x-edge lanes), else 0
   unroll<0, L::Q>([&](auto qc) {
     constexpr int q = decltype(qc)::value;
     constexpr int cx = L::cx[q], cy = L::cy[q], cz = L::cz[q];
-    if constexpr (q == 0) {
-      g[0] = a.src[self];
-    } else {
-      bool fy = false, fz = false, gh = false;
+    ghm[q] = 0u;
+    uint32_t sf = ~0u, si = self;   // ~0u: source fluid, 0: bounce-back
+    if constexpr (q != 0) {
+      const RowWords& r = rw[1 - cz][1 - cy];
+      const uint32_t r0 = lane_rank(r.mid, r.base);
+      if constexpr (cx == 0) {
+        sf = lane_mask(r.mid, lane);
+        si = r0;
+      } else if constexpr (cx > 0) {   // source x - 1: slot r0 - fluid(x - 1)
+        sf = lane_mask((r.mid << 1) | (r.lo >> 63), lane);
+        si = (lane == 0 ? r.end_lo : r0) + sf;
+        if constexpr (XE) {
+          if (x0) { sf = lane_mask(r.mid, lane); si = r0; ghm[q] = sf; }
+        }
+      } else {                          // source x + 1: slot r0 + fluid(x)
+        const uint32_t f0 = lane_mask(r.mid, lane);
+        sf = lane_mask((r.mid >> 1) | (r.hi << 63), lane);
+        si = lane == 63 ? r.base_hi : r0 - f0;
+        if constexpr (XE) {
+          if (x1) { sf = f0; si = r0; ghm[q] = sf; }
+        }
+      }
+    }
+    // direction read by a fluid source: q, or its mirror image
+    int k = q;
+    if constexpr (YZE && q != 0) {
+      bool fy = false, fz = false;
       if constexpr (cy > 0) fy = y0;
       if constexpr (cy < 0) fy = y1;
       if constexpr (cz > 0) fz = z0;
       if constexpr (cz < 0) fz = z1;
-      if constexpr (cx > 0) gh = x0;
-      if constexpr (cx < 0) gh = x1;
       constexpr int kY = L::my[q], kZ = L::mz[q], kYZ = L::mz[L::my[q]];
-      const int k = fy ? (fz ? kYZ : kY) : (fz ? kZ : q);
-      const RowView& r = rv[1 - cz][1 - cy];
-      uint32_t sf, si;   // source fluid?, source compact index
-      if constexpr (cx == 0) {
-        sf = r.f0;
-        si = r.r0;
-      } else if constexpr (cx > 0) {
-        sf = gh ? r.f0 : r.fm;
-        si = gh ? r.r0 : r.r0 - r.fm;
-      } else {
-        sf = gh ? r.f0 : r.fp;
-        si = gh ? r.r0 : r.r0 + r.f0;
-      }
-      const T* ptr = sf ? a.src + (uint64_t)k * a.ps + si
-                        : a.src + (uint64_t)L::opp[q] * a.ps + self;   // bounce-back
-      T v = *ptr;
-      if constexpr (cx != 0) {
-        if (gh && sf) {
-          const int ys = fy ? y : y - cy, zs = fz ? z : z - cz;
-          v += ghost_term<L, LINEAR, T>(a.bp_src, cx > 0 ? 0 : 1, (uint32_t)fm.nz * fm.ny,
-                                        (uint32_t)zs * fm.ny + ys, cx > 0 ? a.drho_in : a.drho_out,
-                                        T(L::w[q]), cx, fy ? -cy : cy, fz ? -cz : cz);
-        }
-      }
-      g[q] = v;
+      k = fy ? (fz ? kYZ : kY) : (fz ? kZ : q);
+    }
+    constexpr int o = L::opp[q];
+    if constexpr (OFF32) {
+      constexpr int first = q < L::group_split ? 0 : L::group_split;
+      const char* base = q < L::group_split ? (const char*)a.src : (const char*)a.src_g1;
+      const uint32_t ck = (uint32_t)(k - first) * a.ps_bytes;
+      const uint32_t co = (uint32_t)(o - first) * a.ps_bytes;
+      const uint32_t off = pick(sf, si * (uint32_t)sizeof(T) + ck, selfb + co);
+      g[q] = *(const T*)(base + off);
+    } else {
+      const uint64_t idx = sf ? (uint64_t)k * a.ps + si : (uint64_t)o * a.ps + self;
+      g[q] = a.src[idx];
     }
   });
+
+  // Ghost populations: add the non-equilibrium extrapolation term.
+  if constexpr (XE) {
+    if (x0 || x1) {
+      unroll<1, L::Q>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        constexpr int cx = L::cx[q], cy = L::cy[q], cz = L::cz[q];
+        if constexpr (cx != 0) {
+          if (ghm[q]) {
+            bool fy = false, fz = false;
+            if constexpr (cy > 0) fy = y0;
+            if constexpr (cy < 0) fy = y1;
+            if constexpr (cz > 0) fz = z0;
+            if constexpr (cz < 0) fz = z1;
+            const int ys = fy ? y : y - cy, zs = fz ? z : z - cz;
+            g[q] += ghost_term<L, LINEAR, T>(a.bp_src, cx > 0 ? 0 : 1, (uint32_t)a.nz * a.ny,
+                                             (uint32_t)zs * a.ny + ys,
+                                             cx > 0 ? a.drho_in : a.drho_out, T(L::w[q]), cx,
+                                             fy ? -cy : cy, fz ? -cz : cz);
+          }
+        }
+      });
+    }
+  }
 
   T drho = T(0), jx = T(0), jy = T(0), jz = T(0);
   unroll<0, L::Q>([&](auto qc) {
@@ -312,53 +443,161 @@ __device__ __forceinline__ T node_update(const StepArgs<T>& a, int y, int z, int
     if constexpr (L::cz[q] == -1) jz -= g[q];
   });
   const T rho = a.rho0 + drho;
-  const T inv = T(1) / rho;
+  const T inv = recip(rho);
   const T ux = jx * inv, uy = jy * inv, uz = jz * inv;
   const T usq15 = T(1.5) * (ux * ux + uy * uy + uz * uz);
   unroll<0, L::Q>([&](auto qc) {
     constexpr int q = decltype(qc)::value;
     const T ge = geq<L, q, LINEAR>(drho, rho, ux, uy, uz, usq15);
     g[q] = g[q] - a.omega * (g[q] - ge);
-    a.dst[(uint64_t)q * a.ps + self] = g[q];
+    out[q][lds_base + self] = g[q];
   });
 
-  if (x0 || x1) {
-    // edge-node moments of the stored state, read by the next step's ghosts
-    T bd, bx, by, bz;
-    stored_moments<L, T>([&](auto qc) { return g[decltype(qc)::value]; }, a.rho0, bd, bx, by, bz);
-    const uint32_t plane = (uint32_t)fm.nz * fm.ny;
-    T* bp = a.bp_dst + (size_t)(x0 ? 0 : 1) * (L::D + 1) * plane + (uint32_t)z * fm.ny + y;
-    bp[0] = bd;
-    bp[plane] = bx;
-    bp[2 * plane] = by;
-    if constexpr (L::D == 3) bp[3 * plane] = bz;
+  if constexpr (XE) {
+    if (x0 || x1) {
+      // edge-node moments of the stored state, read by the next step's ghosts
+      T bd, bx, by, bz;
+      stored_moments<L, T>([&](auto qc) { return g[decltype(qc)::value]; }, a.rho0, bd, bx, by, bz);
+      const uint32_t plane = (uint32_t)a.nz * a.ny;
+      T* bp = a.bp_dst + (size_t)(x0 ? 0 : 1) * (L::D + 1) * plane + row_self;
+      bp[0] = bd;
+      bp[plane] = bx;
+      bp[2 * plane] = by;
+      if constexpr (L::D == 3) bp[3 * plane] = bz;
+    }
   }
   return jx;
 }
 
-// Tile of logical block b: word w (64 x), rows y0..y0+3, plane z.  With
-// xcd_remap the hardware block id, which the dispatcher deals round-robin over
-// the 8 XCDs, is mapped so that each XCD gets one contiguous range of tiles:
-// neighbouring tiles then share that XCD's L2 for the lines at their edges.
-__device__ __forceinline__ int logical_block(int hw, int blocks, int remap) {
-  if (!remap) return hw;
-  const int per = (blocks + 7) >> 3;
-  return (hw & 7) * per + (hw >> 3);
+// Picks the specialisation of node_update for a wave's (y, z, w).
+template <class L, class T, bool LINEAR, bool OFF32>
+__device__ __forceinline__ T wave_update(const StepArgs<T>& a, int y, int z, int w, int lane,
+                                         T (*out)[kThreads], uint32_t lds_base) {
+  const bool yze = y == 0 || y == a.ny - 1 || (L::D == 3 && (z == 0 || z == a.nz - 1));
+  const bool xe = w == 0 || w == ((a.nx - 1) >> 6);
+  if (yze) {
+    if (xe) return node_update<L, T, LINEAR, OFF32, true, true>(a, y, z, w, lane, out, lds_base);
+    return node_update<L, T, LINEAR, OFF32, true, false>(a, y, z, w, lane, out, lds_base);
+  }
+  if (xe) return node_update<L, T, LINEAR, OFF32, false, true>(a, y, z, w, lane, out, lds_base);
+  return node_update<L, T, LINEAR, OFF32, false, false>(a, y, z, w, lane, out, lds_base);
 }
 
-// One time step of one domain.  FLUX: also store the block's summed
-// x-momentum (FP64) in partial[b].
-template <class L, class T, bool FLUX, bool LINEAR>
-__global__ __launch_bounds__(kThreads) void k_step(StepArgs<T> a) {
-  const int b = logical_block(blockIdx.x, a.blocks, a.xcd_remap);
-  if (b >= a.blocks) return;   // whole block: padding of the remapped grid
-  const int w = b % a.fm.nw;
-  const int r = b / a.fm.nw;
-  const int z = r / a.tiles_y;
-  const int y = uniform((r % a.tiles_y) * kRows + (int)threadIdx.y);
+// Order in which tiles meet the hardware.  The dispatcher deals block ids
+// round-robin over the 8 XCDs (block h runs on XCD h % 8), each with its own
+// L2.  Neighbouring tiles share the cache lines at the ends of their compact
+// ranges, so they should run on one XCD; and all XCDs should work on one
+// compact region at a time, so that DRAM pages stay open and the memory-side
+// cache catches what the L2s both fetch.  Modes:
+//   0  hardware order (neighbouring tiles on different XCDs);
+//   1  each XCD gets one contiguous eighth of the tiles;
+//   c >= 2  chunks of `chunk` consecutive tiles are dealt round-robin to the
+//      XCDs, so the XCDs work side by side on eight neighbouring chunks.
+// Modes 1 and 2+ need a grid padded to a multiple of 8 (mode 1) or
+// 8 * chunk (mode 2+); blocks whose logical tile is past the end exit.
+template <class T>
+__device__ __forceinline__ int logical_block(int hw, const StepArgs<T>& a) {
+  if (a.xcd_remap == 0) return hw;
+  if (a.xcd_remap == 1) {
+    const int per = (a.blocks + 7) >> 3;
+    return (hw & 7) * per + (hw >> 3);
+  }
+  const uint32_t k = (uint32_t)hw >> 3;
+  const uint32_t kc = a.dv_chunk.div(k);
+  return (int)(kc * 8u * a.dv_chunk.d + (uint32_t)(hw & 7) * a.dv_chunk.d + (k - kc * a.dv_chunk.d));
+}
+
+// One time step of one domain.  A block's four waves cover one segment (S
+// consecutive 64-wide words) of each of 4 / S rows of one z plane, one word per
+// wave.  Tile order: logical_block, or with band > 0 the banded order: XCD
+// h % 8 takes bands h % 8, h % 8 + 8, ... of `band` tile rows and walks each
+// band plane by plane, so the rows a node pulls from (y +- 1, z +- 1) are
+// processed close together in time on one XCD and the cache lines two waves
+// share are fetched once.  The block gathers its post-collision populations in
+// LDS and then writes each segment as whole aligned lines (padding slots get
+// zero).  FLUX: each wave also stores the FP64 sum of its 64 nodes'
+// x-momentum at the index of its bitmap word, (z ny + y) nw + w, so the flux
+// does not depend on the tiling.
+template <class L, class T, bool FLUX, bool LINEAR, bool OFF32>
+__global__ __launch_bounds__(kThreads) void k_step(const StepArgs<T> a) {
+  __shared__ T out[L::Q][kThreads];
+  __shared__ uint32_t seg_first[kRows], seg_count[kRows];
+  int tx, ty, z;
+  if (a.band > 0) {
+    const uint32_t k = blockIdx.x >> 3;
+    const uint32_t round = a.dv_band_blocks.div(k);
+    const uint32_t kk = k - round * a.dv_band_blocks.d;
+    const int bi = (int)(round * 8u + (blockIdx.x & 7u));
+    if (bi >= a.nbands) return;   // whole block: padding band
+    const uint32_t zp = a.dv_band_plane.div(kk);
+    const uint32_t rem = kk - zp * a.dv_band_plane.d;
+    const uint32_t tyl = a.dv_tiles_x.div(rem);
+    tx = (int)(rem - tyl * (uint32_t)a.tiles_x);
+    ty = bi * a.band + (int)tyl;
+    z = (int)zp;
+    if (ty >= a.tiles_y) return;   // whole block: past the last tile row
+  } else {
+    const int b = logical_block(blockIdx.x, a);
+    if (b >= a.blocks) return;     // whole block: padding of the remapped grid
+    const uint32_t r = a.dv_tiles_x.div((uint32_t)b);
+    tx = b - (int)(r * (uint32_t)a.tiles_x);
+    const uint32_t zz = a.dv_tiles_y.div(r);
+    ty = (int)(r - zz * (uint32_t)a.tiles_y);
+    z = (int)zz;
+  }
+  const int S = a.seg;
+  const int wave = threadIdx.y, lane = threadIdx.x;
+  const int j = uniform(wave / S);                  // row of the tile
+  const int y = uniform(ty * (kRows / S) + j);
+  const int w0 = tx * S;                            // first word of the segment
+  const int w = uniform(w0 + wave % S);
+  z = uniform(z);
+  const bool row_ok = y < a.ny;
+  const uint32_t row = (uint32_t)z * (uint32_t)a.ny + (uint32_t)y;
+  // segment of this wave's row: first slot and number of fluid nodes
+  uint32_t first = 0u, count = 0u;
+  if (row_ok) {
+    first = a.pfx[row * (uint32_t)a.nw + (uint32_t)w0];
+    const uint64_t* wd = a.bits + row * (uint32_t)(a.nw + 2) + 1u;
+    const int we = min(w0 + S, a.nw);
+    for (int i = w0; i < we; ++i) count += (uint32_t)__popcll(wd[i]);
+  }
+  if (wave % S == 0 && lane == 0) {
+    seg_first[j] = first;
+    seg_count[j] = count;
+  }
   T jx = T(0);
-  if (y < a.fm.ny) jx = node_update<L, T, LINEAR>(a, y, uniform(z), uniform(w), threadIdx.x);
-  if constexpr (FLUX) block_sum_store<kThreads>((double)jx, a.partial + b);
+  if (row_ok && w < a.nw) {
+    const uint32_t lds_base = (uint32_t)(j * S * kWave) - first;
+    jx = wave_update<L, T, LINEAR, OFF32>(a, y, z, w, lane, out, lds_base);
+  }
+  if constexpr (FLUX) {
+    if (row_ok && w < a.nw) {
+      const double s = wave_sum((double)jx);
+      if (lane == 0) a.partial[(size_t)row * a.nw + w] = s;
+    }
+  }
+  __syncthreads();
+  // whole-line stores: thread t writes position t of its row's segment
+  const int t = wave * kWave + lane;
+  const int jj = t / (S * kWave);
+  const uint32_t r = (uint32_t)(t - jj * S * kWave);
+  const uint32_t n = seg_count[jj];
+  const uint32_t lim = (n + a.align - 1u) & ~(a.align - 1u);
+  if (r < lim) {
+    const uint32_t slot = seg_first[jj] + r;
+    unroll<0, L::Q>([&](auto qc) {
+      constexpr int q = decltype(qc)::value;
+      const T v = r < n ? out[q][t] : T(0);
+      if constexpr (OFF32) {
+        constexpr int f = q < L::group_split ? 0 : L::group_split;
+        char* base = q < L::group_split ? (char*)a.dst : (char*)a.dst_g1;
+        *(T*)(base + (slot * (uint32_t)sizeof(T) + (uint32_t)(q - f) * a.ps_bytes)) = v;
+      } else {
+        a.dst[(uint64_t)q * a.ps + slot] = v;
+      }
+    });
+  }
 }
 
 // ------------------------------------------------------------ set-up kernels
@@ -441,6 +680,48 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_add(uint32_t* __restrict__ 
                                                          uint64_t n) {
   const uint64_t i = (uint64_t)blockIdx.x * kScanBlock + threadIdx.x;
   if (i < n) out[i] += block_tot[blockIdx.x];
+}
+
+// Padded size of every segment (S words of a row): its fluid count rounded up
+// to `align` slots.
+__global__ __launch_bounds__(256) void k_seg_sizes(const uint32_t* __restrict__ count,
+                                                   uint32_t* __restrict__ seg_size, uint64_t nsegs,
+                                                   int nw, int S, int segs_per_row, uint32_t align) {
+  const uint64_t sg = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  if (sg >= nsegs) return;
+  const uint64_t row = sg / segs_per_row;
+  const int w0 = (int)(sg % segs_per_row) * S;
+  const int we = min(w0 + S, nw);
+  uint32_t n = 0;
+  for (int i = w0; i < we; ++i) n += count[row * nw + i];
+  seg_size[sg] = (n + align - 1u) & ~(align - 1u);
+}
+
+// Slot of the first fluid node of every word: the segment's first slot plus the
+// fluid nodes of the segment's earlier words.
+__global__ __launch_bounds__(256) void k_word_pfx(const uint32_t* __restrict__ count,
+                                                  const uint32_t* __restrict__ seg_first,
+                                                  uint32_t* __restrict__ pfx, uint64_t nwords, int nw,
+                                                  int S, int segs_per_row) {
+  const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= nwords) return;
+  const uint64_t row = i / nw;
+  const int w = (int)(i % nw);
+  const int s = w / S;
+  uint32_t p = seg_first[row * segs_per_row + s];
+  for (int k = s * S; k < w; ++k) p += count[row * nw + k];
+  pfx[i] = p;
+}
+
+// Slot of every node (x fastest), -1 for solids.
+__global__ __launch_bounds__(256) void k_slot_map(FluidMap fm, int32_t* __restrict__ map) {
+  const uint64_t m = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  if (m >= (uint64_t)fm.nx * fm.ny * fm.nz) return;
+  const int x = (int)(m % fm.nx);
+  const uint64_t r = m / fm.nx;
+  bool fluid;
+  const uint32_t k = fm.rank(x, (int)(r % fm.ny), (int)(r / fm.ny), fluid);
+  map[m] = fluid ? (int32_t)k : -1;
 }
 
 // Rest state: g_i = w_i (rho(x) - rho0), rho uniform (mode 0) or linear in x
@@ -541,8 +822,11 @@ __global__ __launch_bounds__(256) void k_flux(const T* __restrict__ f, uint64_t 
   const uint64_t k = (uint64_t)blockIdx.x * 256 + threadIdx.x;
   T jx = T(0);
   if (k < n_fluid) {
-    unroll<L::xp_begin, L::xp_end>([&](auto qc) { jx += f[(uint64_t)decltype(qc)::value * ps + k]; });
-    unroll<L::xm_begin, L::xm_end>([&](auto qc) { jx -= f[(uint64_t)decltype(qc)::value * ps + k]; });
+    unroll<1, L::Q>([&](auto qc) {
+      constexpr int q = decltype(qc)::value;
+      if constexpr (L::cx[q] == 1) jx += f[(uint64_t)q * ps + k];
+      if constexpr (L::cx[q] == -1) jx -= f[(uint64_t)q * ps + k];
+    });
   }
   block_sum_store<256>((double)jx, partial + blockIdx.x);
 }

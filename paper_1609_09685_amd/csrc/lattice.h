@@ -1,10 +1,14 @@
 // Lattice velocity sets of the solver: D2Q9 and D3Q19 (Qian, d'Humieres &
 // Lallemand 1992), the two lattices the paper uses for its 2D and 3D cases.
 //
-// Direction order (this library's own): the rest direction, then the
-// directions moving towards +x, then those moving towards -x, then those with
-// no x component.  Grouping by the x component keeps the inlet/outlet ghost
-// logic to compile-time ranges.
+// Direction order (this library's own, and also the order of the population
+// arrays in memory): the rest direction first, then the moving directions in
+// opposite pairs, (1, 2), (3, 4), ...: opp(i) = i + 1 for odd i, i - 1 for even
+// i > 0.  The arrays form groups of at most 10 that are closed under opp, my
+// and mz (D3Q19: the in-plane directions 0..8, and 9..18), so everything one
+// node loads for one direction (streaming, mirrored, or bounce-back) lies in
+// one group, which lets the kernel address a group with 32-bit offsets.  The
+// first nine D3Q19 directions are the D2Q9 set.
 //
 //   opp(i): c_opp = -c_i        (halfway bounce-back)
 //   my(i):  c_y flipped          (symmetric plane normal to y)
@@ -20,32 +24,31 @@ namespace lbm {
 struct D2Q9 {
   static constexpr int Q = 9;
   static constexpr int D = 2;
-  static constexpr int cx[Q] = {0, 1, 1, 1, -1, -1, -1, 0, 0};
-  static constexpr int cy[Q] = {0, 0, 1, -1, 0, 1, -1, 1, -1};
+  static constexpr int cx[Q] = {0, 1, -1, 0, 0, 1, -1, 1, -1};
+  static constexpr int cy[Q] = {0, 0, 0, 1, -1, 1, -1, -1, 1};
   static constexpr int cz[Q] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-  static constexpr double w[Q] = {4.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 9,
-                                  1.0 / 36, 1.0 / 36, 1.0 / 9, 1.0 / 9};
-  static constexpr int opp[Q] = {0, 4, 6, 5, 1, 3, 2, 8, 7};
-  static constexpr int my[Q] = {0, 1, 3, 2, 4, 6, 5, 8, 7};
+  static constexpr double w[Q] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
+                                  1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+  static constexpr int opp[Q] = {0, 2, 1, 4, 3, 6, 5, 8, 7};
+  static constexpr int my[Q] = {0, 1, 2, 4, 3, 7, 8, 5, 6};
   static constexpr int mz[Q] = {0, 1, 2, 3, 4, 5, 6, 7, 8};
-  // directions with c_x = +1 are [xp_begin, xp_end), c_x = -1 [xm_begin, xm_end)
-  static constexpr int xp_begin = 1, xp_end = 4, xm_begin = 4, xm_end = 7;
+  static constexpr int group_split = 9;   // one group
 };
 
 struct D3Q19 {
   static constexpr int Q = 19;
   static constexpr int D = 3;
-  static constexpr int cx[Q] = {0, 1, 1, 1, 1, 1, -1, -1, -1, -1, -1, 0, 0, 0, 0, 0, 0, 0, 0};
-  static constexpr int cy[Q] = {0, 0, 1, -1, 0, 0, 0, 1, -1, 0, 0, 1, -1, 0, 0, 1, -1, 1, -1};
-  static constexpr int cz[Q] = {0, 0, 0, 0, 1, -1, 0, 0, 0, 1, -1, 0, 0, 1, -1, 1, -1, -1, 1};
+  static constexpr int cx[Q] = {0, 1, -1, 0, 0, 1, -1, 1, -1, 0, 0, 1, -1, 1, -1, 0, 0, 0, 0};
+  static constexpr int cy[Q] = {0, 0, 0, 1, -1, 1, -1, -1, 1, 0, 0, 0, 0, 0, 0, 1, -1, 1, -1};
+  static constexpr int cz[Q] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 1, -1, 1, -1, -1, 1, 1, -1, -1, 1};
   static constexpr double w[Q] = {
-      1.0 / 3,  1.0 / 18, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 18,
-      1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 18, 1.0 / 18, 1.0 / 18,
-      1.0 / 18, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
-  static constexpr int opp[Q] = {0, 6, 8, 7, 10, 9, 1, 3, 2, 5, 4, 12, 11, 14, 13, 16, 15, 18, 17};
-  static constexpr int my[Q] = {0, 1, 3, 2, 4, 5, 6, 8, 7, 9, 10, 12, 11, 13, 14, 18, 17, 16, 15};
-  static constexpr int mz[Q] = {0, 1, 2, 3, 5, 4, 6, 7, 8, 10, 9, 11, 12, 14, 13, 17, 18, 15, 16};
-  static constexpr int xp_begin = 1, xp_end = 6, xm_begin = 6, xm_end = 11;
+      1.0 / 3,  1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 36, 1.0 / 36,
+      1.0 / 36, 1.0 / 36, 1.0 / 18, 1.0 / 18, 1.0 / 36, 1.0 / 36, 1.0 / 36,
+      1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+  static constexpr int opp[Q] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17};
+  static constexpr int my[Q] = {0, 1, 2, 4, 3, 7, 8, 5, 6, 9, 10, 11, 12, 13, 14, 18, 17, 16, 15};
+  static constexpr int mz[Q] = {0, 1, 2, 3, 4, 5, 6, 7, 8, 10, 9, 13, 14, 11, 12, 17, 18, 15, 16};
+  static constexpr int group_split = 9;   // groups [0, 9) and [9, 19)
 };
 
 namespace detail {
@@ -60,16 +63,18 @@ constexpr int find(int x, int y, int z) {
 template <class L>
 constexpr bool tables_consistent() {
   double wsum = 0;
+  if (L::cx[0] != 0 || L::cy[0] != 0 || L::cz[0] != 0) return false;
   for (int i = 0; i < L::Q; ++i) {
     if (L::opp[i] != find<L>(-L::cx[i], -L::cy[i], -L::cz[i])) return false;
     if (L::my[i] != find<L>(L::cx[i], -L::cy[i], L::cz[i])) return false;
     if (L::mz[i] != find<L>(L::cx[i], L::cy[i], -L::cz[i])) return false;
-    int n = (L::cx[i] != 0) + (L::cy[i] != 0) + (L::cz[i] != 0);
     if (find<L>(L::cx[i], L::cy[i], L::cz[i]) != i) return false;  // distinct vectors
-    if (i >= L::xp_begin && i < L::xp_end && L::cx[i] != 1) return false;
-    if (i >= L::xm_begin && i < L::xm_end && L::cx[i] != -1) return false;
-    if ((i < L::xp_begin || i >= L::xm_end) && L::cx[i] != 0) return false;
-    (void)n;
+    if (i > 0 && L::opp[i] != (i % 2 ? i + 1 : i - 1)) return false;  // adjacent pairs
+    const bool g = i < L::group_split;   // groups closed under opp, my, mz
+    if (g != (L::opp[i] < L::group_split) || g != (L::my[i] < L::group_split) ||
+        g != (L::mz[i] < L::group_split))
+      return false;
+    if (L::Q - L::group_split > 10 || L::group_split > 10) return false;
     wsum += L::w[i];
   }
   return wsum > 1.0 - 1e-15 && wsum < 1.0 + 1e-15;

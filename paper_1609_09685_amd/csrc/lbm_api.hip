@@ -54,15 +54,20 @@ struct Layout {
   int Q, D;
   size_t esize;          // bytes per population value
   int nw;                // bitmap words per row
+  int S;                 // words per segment (and per step tile row): 1, 2 or 4
+  int segs_per_row;      // ceil(nw / S)
+  uint32_t align;        // slots per 128 bytes
   uint64_t rows;         // ny * nz
+  uint64_t nsegs;        // rows * segs_per_row
   uint64_t n_fluid;
-  uint64_t ps;           // elements per direction array (n_fluid padded to 64)
+  uint64_t ps;           // slots per direction array: room for every segment's padding
   size_t f_bytes;
-  int tiles_y, blocks, grid;   // step tiles; grid = blocks rounded up to 8 (XCD remap)
-  int scan_blocks;
-  size_t off_bits, off_pfx, off_count, off_scan, off_bplane, off_partial, off_scalar, work_bytes;
+  int scan_blocks, seg_scan_blocks;
+  size_t off_bits, off_pfx, off_count, off_scan, off_seg, off_seg_scan, off_bplane, off_partial,
+      off_scalar, work_bytes;
   size_t bplane_one;     // elements of one parity of the boundary-plane array
   int partials;          // capacity of the partial array
+  int chunks;            // capacity of the chunk-sum array
 };
 
 lbm_status validate_geom(const lbm_geom* g) {
@@ -89,22 +94,33 @@ lbm_status make_layout(const lbm_geom* g, Layout* L) {
   L->D = g->lattice == LBM_D2Q9 ? 2 : 3;
   L->esize = g->precision == LBM_FP64 ? 8 : 4;
   L->nw = (g->nx + kWave - 1) / kWave;
+  L->S = L->nw >= 4 ? 4 : (L->nw >= 2 ? 2 : 1);
+  L->segs_per_row = (L->nw + L->S - 1) / L->S;
+  L->align = (uint32_t)(128 / L->esize);
   L->rows = (uint64_t)g->ny * g->nz;
+  L->nsegs = L->rows * L->segs_per_row;
   L->n_fluid = (uint64_t)g->n_fluid;
-  L->ps = align_up(L->n_fluid ? L->n_fluid : 1, 64);
+  // every segment may need up to align - 1 padding slots
+  L->ps = align_up(L->n_fluid + (uint64_t)(L->align - 1) * L->nsegs, 64);
+  if (L->ps == 0) L->ps = 64;
   if (L->ps >= (1ull << 32) || (uint64_t)g->nx * g->ny * g->nz >= (1ull << 40))
-    return fail(LBM_EINVAL, "domain too large: more than 2^32 fluid nodes");
+    return fail(LBM_EINVAL, "domain too large: more than 2^32 population slots");
   L->f_bytes = (size_t)L->Q * L->ps * L->esize;
-  L->tiles_y = (g->ny + kRows - 1) / kRows;
-  const uint64_t blocks = (uint64_t)L->nw * L->tiles_y * g->nz;
-  if (blocks >= (1ull << 31) - 8) return fail(LBM_EINVAL, "too many blocks");
-  L->blocks = (int)blocks;
-  L->grid = (int)align_up(blocks, 8);
+  {
+    const int rows_per_tile = kRows / L->S;
+    const uint64_t b = (uint64_t)L->segs_per_row * ((g->ny + rows_per_tile - 1) / rows_per_tile) * g->nz;
+    if (b * 8 >= (1ull << 31)) return fail(LBM_EINVAL, "too many blocks");
+  }
   const uint64_t nwords = L->rows * L->nw;
+  if (L->rows * (uint64_t)(L->nw + 2) >= (1ull << 31))
+    return fail(LBM_EINVAL, "too many bitmap words");
   L->scan_blocks = (int)((nwords + kScanBlock - 1) / kScanBlock);
-  const uint64_t flux_blocks = (L->n_fluid + 255) / 256;
-  L->partials = (int)(blocks > flux_blocks ? blocks : flux_blocks);
-  if (L->partials < 1) L->partials = 1;
+  L->seg_scan_blocks = (int)((L->nsegs + kScanBlock - 1) / kScanBlock);
+  // one flux partial per bitmap word (step) or per 256 slots (flux pass)
+  const uint64_t flux_blocks = (L->ps + 255) / 256;
+  const uint64_t parts = nwords > flux_blocks ? nwords : flux_blocks;
+  L->partials = (int)(parts < 1 ? 1 : parts);
+  L->chunks = (L->partials + kChunk - 1) / kChunk;
   L->bplane_one = (size_t)2 * (L->D + 1) * g->nz * g->ny;
   size_t off = 0;
   L->off_bits = off;
@@ -115,10 +131,14 @@ lbm_status make_layout(const lbm_geom* g, Layout* L) {
   off = align_up(off + nwords * 4, 256);
   L->off_scan = off;
   off = align_up(off + (size_t)L->scan_blocks * 4, 256);
+  L->off_seg = off;
+  off = align_up(off + (size_t)L->nsegs * 4, 256);
+  L->off_seg_scan = off;
+  off = align_up(off + (size_t)L->seg_scan_blocks * 4, 256);
   L->off_bplane = off;
   off = align_up(off + 2 * L->bplane_one * L->esize, 256);
   L->off_partial = off;
-  off = align_up(off + (size_t)L->partials * 8, 256);
+  off = align_up(off + (size_t)(L->partials + L->chunks) * 8, 256);
   L->off_scalar = off;
   off = align_up(off + 64, 256);
   L->work_bytes = off;
@@ -139,11 +159,15 @@ struct lbm_ctx {
   int64_t steps;
   int linear_eq;
   int xcd_remap;
+  uint64_t n_slots;    // slots in use per direction array (fluid nodes + padding)
+  int band;            // 0 or tile rows per band (banded tile order)
 
   uint64_t* bits() const { return (uint64_t*)(work + L.off_bits); }
   uint32_t* pfx() const { return (uint32_t*)(work + L.off_pfx); }
   uint32_t* count() const { return (uint32_t*)(work + L.off_count); }
   uint32_t* scan() const { return (uint32_t*)(work + L.off_scan); }
+  uint32_t* seg() const { return (uint32_t*)(work + L.off_seg); }
+  uint32_t* seg_scan() const { return (uint32_t*)(work + L.off_seg_scan); }
   void* bplane(int p) const { return work + L.off_bplane + (size_t)p * L.bplane_one * L.esize; }
   double* partial() const { return (double*)(work + L.off_partial); }
   double* scalar() const { return (double*)(work + L.off_scalar); }
@@ -161,19 +185,55 @@ struct lbm_ctx {
 
 namespace {
 
+// Every direction group (at most 10 arrays of ps values) spans less than
+// 4 GiB: the step kernel can use 32-bit group-relative offsets.
+bool off32_ok(const lbm_ctx* c) { return 10ull * c->L.ps * c->L.esize < (1ull << 32); }
+
+// Divisor d >= 1 for FastDiv: l = ceil(log2 d), m = 2^32 (2^l - d) / d + 1.
+FastDiv make_fastdiv(uint32_t d) {
+  FastDiv f;
+  f.d = d < 1 ? 1 : d;
+  f.l = 0;
+  while ((1ull << f.l) < f.d) ++f.l;
+  f.m = (uint32_t)(((1ull << 32) * ((1ull << f.l) - f.d)) / f.d + 1);
+  return f;
+}
+
 template <class T>
 StepArgs<T> step_args(const lbm_ctx* c) {
   StepArgs<T> a;
   a.src = (const T*)c->f[c->parity];
   a.dst = (T*)c->f[c->parity ^ 1];
-  a.fm = c->fmap();
+  const int split = c->g.lattice == LBM_D2Q9 ? D2Q9::group_split : D3Q19::group_split;
+  a.src_g1 = a.src + (uint64_t)split * c->L.ps;
+  a.dst_g1 = a.dst + (uint64_t)split * c->L.ps;
+  a.ps_bytes = off32_ok(c) ? (uint32_t)(c->L.ps * sizeof(T)) : 0u;
+  a.bits = c->bits();
+  a.pfx = c->pfx();
   a.bp_src = (const T*)c->bplane(c->parity);
   a.bp_dst = (T*)c->bplane(c->parity ^ 1);
   a.partial = c->partial();
   a.ps = c->L.ps;
-  a.tiles_y = c->L.tiles_y;
-  a.blocks = c->L.blocks;
+  a.nx = c->g.nx;
+  a.ny = c->g.ny;
+  a.nz = c->g.nz;
+  a.nw = c->L.nw;
+  a.seg = c->L.S;
+  a.align = c->L.align;
+  a.tiles_x = c->L.segs_per_row;
+  const int rows = kRows / c->L.S;
+  a.tiles_y = (c->g.ny + rows - 1) / rows;
+  a.blocks = a.tiles_x * a.tiles_y * c->g.nz;
   a.xcd_remap = c->xcd_remap;
+  // mode >= 2: chunks of (mode - 1) rows of tiles
+  a.chunk = c->xcd_remap >= 2 ? (c->xcd_remap - 1) * a.tiles_x : 1;
+  a.dv_tiles_x = make_fastdiv((uint32_t)a.tiles_x);
+  a.dv_tiles_y = make_fastdiv((uint32_t)a.tiles_y);
+  a.dv_chunk = make_fastdiv((uint32_t)a.chunk);
+  a.band = c->band;
+  a.nbands = a.band > 0 ? (a.tiles_y + a.band - 1) / a.band : 0;
+  a.dv_band_blocks = make_fastdiv((uint32_t)(a.band > 0 ? c->g.nz * a.band * a.tiles_x : 1));
+  a.dv_band_plane = make_fastdiv((uint32_t)(a.band > 0 ? a.band * a.tiles_x : 1));
   a.omega = (T)(1.0 / c->tau);
   a.rho0 = (T)c->g.rho0;
   a.drho_in = (T)(c->rho_in - c->g.rho0);
@@ -187,16 +247,23 @@ uint64_t n_nodes(const lbm_ctx* c) { return (uint64_t)c->g.nx * c->g.ny * c->g.n
 template <class Lat, class T>
 lbm_status launch_steps(lbm_ctx* c, int64_t n, bool flux_last) {
   const dim3 block(kWave, kRows);
-  const int grid = c->xcd_remap ? c->L.grid : c->L.blocks;
   for (int64_t s = 0; s < n; ++s) {
     StepArgs<T> a = step_args<T>(c);
+    int grid = c->xcd_remap == 0 ? a.blocks
+               : (int)align_up((size_t)a.blocks, (size_t)(c->xcd_remap == 1 ? 8 : 8 * a.chunk));
+    if (a.band > 0)   // whole rounds of 8 bands, one per XCD
+      grid = (int)(align_up((size_t)a.nbands, 8) * a.dv_band_blocks.d);
     const bool flux = flux_last && s == n - 1;
-    if (c->linear_eq) {
-      if (flux) k_step<Lat, T, true, true><<<grid, block, 0, c->stream>>>(a);
-      else k_step<Lat, T, false, true><<<grid, block, 0, c->stream>>>(a);
-    } else {
-      if (flux) k_step<Lat, T, true, false><<<grid, block, 0, c->stream>>>(a);
-      else k_step<Lat, T, false, false><<<grid, block, 0, c->stream>>>(a);
+    const int variant = (flux ? 1 : 0) | (c->linear_eq ? 2 : 0) | (off32_ok(c) ? 4 : 0);
+    switch (variant) {
+      case 0: k_step<Lat, T, false, false, false><<<grid, block, 0, c->stream>>>(a); break;
+      case 1: k_step<Lat, T, true, false, false><<<grid, block, 0, c->stream>>>(a); break;
+      case 2: k_step<Lat, T, false, true, false><<<grid, block, 0, c->stream>>>(a); break;
+      case 3: k_step<Lat, T, true, true, false><<<grid, block, 0, c->stream>>>(a); break;
+      case 4: k_step<Lat, T, false, false, true><<<grid, block, 0, c->stream>>>(a); break;
+      case 5: k_step<Lat, T, true, false, true><<<grid, block, 0, c->stream>>>(a); break;
+      case 6: k_step<Lat, T, false, true, true><<<grid, block, 0, c->stream>>>(a); break;
+      default: k_step<Lat, T, true, true, true><<<grid, block, 0, c->stream>>>(a); break;
     }
     c->parity ^= 1;
     c->steps += 1;
@@ -233,8 +300,8 @@ lbm_status launch_fields(lbm_ctx* c, const float* rho, const float* u) {
 
 template <class Lat, class T>
 lbm_status launch_flux(lbm_ctx* c, int* nparts) {
-  const unsigned nb = grid_1d(c->L.n_fluid ? c->L.n_fluid : 1);
-  k_flux<Lat, T><<<nb, 256, 0, c->stream>>>((const T*)c->f[c->parity], c->L.n_fluid, c->L.ps,
+  const unsigned nb = grid_1d(c->n_slots ? c->n_slots : 1);
+  k_flux<Lat, T><<<nb, 256, 0, c->stream>>>((const T*)c->f[c->parity], c->n_slots, c->L.ps,
                                               c->partial());
   HIP_TRY(hipGetLastError());
   *nparts = (int)nb;
@@ -288,7 +355,11 @@ template <class Lat, class T> struct Bplane {
 
 // Reduces n partials of the last flux pass into scalar[0] and reads it back.
 lbm_status reduce_flux(lbm_ctx* c, int n, double* q) {
-  k_reduce<<<1, 1024, 0, c->stream>>>(c->partial(), n, 1.0 / c->g.nx, c->scalar());
+  const int nch = (n + kChunk - 1) / kChunk;
+  double* chunk = c->partial() + c->L.partials;
+  k_reduce_chunks<<<nch, 1024, 0, c->stream>>>(c->partial(), n, chunk);
+  HIP_TRY(hipGetLastError());
+  k_reduce_final<<<1, 1024, 0, c->stream>>>(chunk, nch, 1.0 / c->g.nx, c->scalar());
   HIP_TRY(hipGetLastError());
   double h = 0.0;
   HIP_TRY(hipMemcpyAsync(&h, c->scalar(), sizeof(double), hipMemcpyDeviceToHost, c->stream));
@@ -304,26 +375,50 @@ lbm_status current_flux(lbm_ctx* c, double* q) {
   return reduce_flux(c, n, q);
 }
 
-// Bitmap, per-word prefix counts, and the fluid count check.
+// Scans n counts in place (exclusive) with the three-pass scan; returns the
+// total through *total (device) - block totals go to tmp.
+lbm_status scan_in_place(lbm_ctx* c, uint32_t* data, uint64_t n, uint32_t* tmp, int nblocks,
+                         uint64_t* total) {
+  k_scan_local<<<nblocks, kScanBlock, 0, c->stream>>>(data, data, tmp, n);
+  HIP_TRY(hipGetLastError());
+  k_scan_totals<<<1, kScanBlock, 0, c->stream>>>(tmp, nblocks, total);
+  HIP_TRY(hipGetLastError());
+  k_scan_add<<<nblocks, kScanBlock, 0, c->stream>>>(data, tmp, n);
+  HIP_TRY(hipGetLastError());
+  return LBM_OK;
+}
+
+// Bitmap, segment-aligned slots of every word, and the fluid count check.
 lbm_status build_fluid_map(lbm_ctx* c) {
   const Layout& L = c->L;
   const uint64_t nwords = L.rows * L.nw;
   k_pack_bits<<<(unsigned)((nwords * 64 + 255) / 256), 256, 0, c->stream>>>(
       c->mask, c->bits(), c->count(), c->g.nx, c->g.ny, c->g.nz, L.nw);
   HIP_TRY(hipGetLastError());
-  k_scan_local<<<L.scan_blocks, kScanBlock, 0, c->stream>>>(c->count(), c->pfx(), c->scan(), nwords);
+  // fluid count: scan a copy of the per-word counts
+  HIP_TRY(hipMemcpyAsync(c->pfx(), c->count(), nwords * 4, hipMemcpyDeviceToDevice, c->stream));
+  uint64_t* totals = (uint64_t*)(c->scalar() + 1);   // [0] fluid nodes, [1] slots
+  lbm_status s = scan_in_place(c, c->pfx(), nwords, c->scan(), L.scan_blocks, totals);
+  if (s != LBM_OK) return s;
+  // padded segment sizes -> first slot of every segment -> slot of every word
+  k_seg_sizes<<<grid_1d(L.nsegs), 256, 0, c->stream>>>(c->count(), c->seg(), L.nsegs, L.nw, L.S,
+                                                         L.segs_per_row, L.align);
   HIP_TRY(hipGetLastError());
-  uint64_t* total = (uint64_t*)(c->scalar() + 1);
-  k_scan_totals<<<1, kScanBlock, 0, c->stream>>>(c->scan(), L.scan_blocks, total);
+  s = scan_in_place(c, c->seg(), L.nsegs, c->seg_scan(), L.seg_scan_blocks, totals + 1);
+  if (s != LBM_OK) return s;
+  k_word_pfx<<<grid_1d(nwords), 256, 0, c->stream>>>(c->count(), c->seg(), c->pfx(), nwords, L.nw,
+                                                      L.S, L.segs_per_row);
   HIP_TRY(hipGetLastError());
-  k_scan_add<<<L.scan_blocks, kScanBlock, 0, c->stream>>>(c->pfx(), c->scan(), nwords);
-  HIP_TRY(hipGetLastError());
-  uint64_t h = 0;
-  HIP_TRY(hipMemcpyAsync(&h, total, sizeof h, hipMemcpyDeviceToHost, c->stream));
+  uint64_t h[2] = {0, 0};
+  HIP_TRY(hipMemcpyAsync(h, totals, sizeof h, hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
-  if (h != L.n_fluid)
+  if (h[0] != L.n_fluid)
     return fail(LBM_EINVAL, "the mask has %llu fluid nodes but geom.n_fluid is %llu",
-                (unsigned long long)h, (unsigned long long)L.n_fluid);
+                (unsigned long long)h[0], (unsigned long long)L.n_fluid);
+  if (h[1] > L.ps)
+    return fail(LBM_EINVAL, "internal: %llu slots exceed the capacity %llu",
+                (unsigned long long)h[1], (unsigned long long)L.ps);
+  c->n_slots = h[1];
   return LBM_OK;
 }
 
@@ -379,6 +474,8 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_geom* geom, const lbm_buffers* bufs
   c->steps = 0;
   c->linear_eq = 0;
   c->xcd_remap = 1;
+  c->n_slots = 0;
+  c->band = 16;
 
   auto fail_free = [&](lbm_status st) { delete c; return st; };
   s = build_fluid_map(c);
@@ -460,7 +557,7 @@ lbm_status lbm_run_to_steady(lbm_ctx* c, double tol, int64_t max_steps, int64_t*
     s = dispatch<Steps>(c, (int64_t)K, true);
     if (s != LBM_OK) return s;
     double q;
-    s = reduce_flux(c, c->L.blocks, &q);
+    s = reduce_flux(c, (int)(c->L.rows * c->L.nw), &q);
     if (s != LBM_OK) return s;
     if (!isfinite(q)) {
       if (steps_out) *steps_out = c->steps;
@@ -505,8 +602,12 @@ lbm_status lbm_set_option(lbm_ctx* c, int32_t option, int64_t value) {
   if (!c) return fail(LBM_EINVAL, "ctx is NULL");
   switch (option) {
     case LBM_OPT_XCD_REMAP:
-      if (value != 0 && value != 1) return fail(LBM_EINVAL, "XCD remap is 0 or 1");
+      if (value < 0 || value > 64) return fail(LBM_EINVAL, "tile order mode is 0..64");
       c->xcd_remap = (int)value;
+      return ok();
+    case LBM_OPT_BAND:
+      if (value < 0 || value > 65536) return fail(LBM_EINVAL, "band is 0 (off) or 1..65536 tile rows");
+      c->band = (int)value;
       return ok();
     case LBM_OPT_LINEAR_EQ:
       if (value != 0 && value != 1) return fail(LBM_EINVAL, "linear equilibrium is 0 or 1");
@@ -515,6 +616,13 @@ lbm_status lbm_set_option(lbm_ctx* c, int32_t option, int64_t value) {
     default:
       return fail(LBM_EINVAL, "unknown option %d", option);
   }
+}
+
+lbm_status lbm_get_slot_map(lbm_ctx* c, int32_t* map) {
+  if (!c || !map) return fail(LBM_EINVAL, "NULL argument");
+  k_slot_map<<<grid_1d((uint64_t)c->g.nx * c->g.ny * c->g.nz), 256, 0, c->stream>>>(c->fmap(), map);
+  HIP_TRY(hipGetLastError());
+  return ok();
 }
 
 lbm_status lbm_lattice(int32_t lattice, int32_t* cv, double* w) {

@@ -58,6 +58,7 @@ _SIGS = {
     "lbm_get_populations": (_c.c_int, [_c.c_void_p, _c.c_void_p]),
     "lbm_set_populations": (_c.c_int, [_c.c_void_p, _c.c_void_p]),
     "lbm_set_option": (_c.c_int, [_c.c_void_p, _c.c_int32, _c.c_int64]),
+    "lbm_get_slot_map": (_c.c_int, [_c.c_void_p, _c.c_void_p]),
     "lbm_lattice": (_c.c_int, [_c.c_int32, _c.c_void_p, _c.c_void_p]),
     "lbm_steps": (_c.c_int, [_c.c_void_p, _c.POINTER(_c.c_int64)]),
     "lbm_knudsen": (_c.c_double, [_c.c_double, _c.c_int32]),
@@ -97,6 +98,7 @@ def _check(status, allow=()):
 
 
 LBM_OPT_XCD_REMAP, LBM_OPT_LINEAR_EQ = 1, 2
+LBM_OPT_BAND = 6
 
 
 def query_sizes(lattice, nx, ny, nz, n_fluid, precision="fp32", check_every=100, rho0=1.0):
@@ -183,8 +185,21 @@ class Solver:
     def set_linear_equilibrium(self, on=True):
         self.set_option(LBM_OPT_LINEAR_EQ, 1 if on else 0)
 
-    def set_xcd_remap(self, on=True):
-        self.set_option(LBM_OPT_XCD_REMAP, 1 if on else 0)
+    def set_xcd_remap(self, mode=1):
+        """Tile order over the XCDs: 0 hardware, 1 contiguous eighths, m >= 2 chunks of
+        m - 1 tile rows dealt round-robin."""
+        self.set_option(LBM_OPT_XCD_REMAP, int(mode))
+
+    def set_band(self, tile_rows):
+        """> 0: banded tile order with bands of `tile_rows` tile rows; 0: off."""
+        self.set_option(LBM_OPT_BAND, tile_rows)
+
+    def configure(self, xcd_remap=None, band=None):
+        """Launch configuration of the step kernel (results are bitwise identical)."""
+        if band is not None:
+            self.set_band(band)
+        if xcd_remap is not None:
+            self.set_xcd_remap(xcd_remap)
 
     # -- state --------------------------------------------------------------
     def reset(self, start="uniform"):
@@ -236,6 +251,13 @@ class Solver:
         _check(self._lib.lbm_get_macro(self._h, rho.data_ptr(), u.data_ptr(),
                                        1 if td == torch.float64 else 0))
         return rho, u
+
+    def slot_map(self):
+        """Device int32 tensor (nz, ny, nx): slot of every node, -1 for solids."""
+        import torch
+        m = torch.empty((self.nz, self.ny, self.nx), dtype=torch.int32, device=self.device)
+        _check(self._lib.lbm_get_slot_map(self._h, m.data_ptr()))
+        return m
 
     def get_populations(self):
         import torch

@@ -25,18 +25,19 @@ def _dtype(solver):
 
 def compact_view(solver, buf=None):
     """The solver's populations as a device tensor (Q, ps): direction-major,
-    fluid nodes only, x-fastest order, padded to ps entries."""
+    one column per slot (fluid nodes and zero padding)."""
     if buf is None:
         buf = solver.get_populations()
     Q = solver.lattice
     return buf.view(_dtype(solver)).view(Q, -1)
 
 
-def fluid_index(solver):
-    """Dense flat indices (x fastest) of the fluid nodes, in compact order."""
+def fluid_slots(solver):
+    """(dense flat indices of the fluid nodes, their slots), as device tensors."""
     import torch
-    m = solver._mask.view(-1)
-    return torch.nonzero(m == 0, as_tuple=False).view(-1)
+    sm = solver.slot_map().view(-1)
+    idx = torch.nonzero(sm >= 0, as_tuple=False).view(-1)
+    return idx, sm[idx].long()
 
 
 def dense_state(solver, buf=None):
@@ -46,7 +47,8 @@ def dense_state(solver, buf=None):
     Q = solver.lattice
     n = solver.nx * solver.ny * solver.nz
     out = torch.zeros((Q, n), dtype=c.dtype, device=c.device)
-    out[:, fluid_index(solver)] = c[:, : solver.n_fluid]
+    idx, slots = fluid_slots(solver)
+    out[:, idx] = c[:, slots]
     return out.view(Q, solver.nz, solver.ny, solver.nx)
 
 
@@ -74,19 +76,21 @@ def from_oracle_f(f, Q, shape, rho0=1.0):
 
 
 def random_state(solver, scale=1e-4, seed=0):
-    """Seeded random deviations g_i = w_i * scale * N(0,1) on every fluid node,
-    written into the solver's current state; returns the dense (Q, nz, ny, nx)
-    view of what was written (0 on solids)."""
+    """Seeded random deviations g_i = w_i * scale * N(0,1) on every fluid node
+    (padding stays zero), written into the solver's current state; returns the
+    dense (Q, nz, ny, nx) view of what was written (0 on solids)."""
     import torch
     Q = solver.lattice
-    buf = torch.empty(solver.f_bytes, dtype=torch.uint8, device=solver.device)
+    buf = torch.zeros(solver.f_bytes, dtype=torch.uint8, device=solver.device)
     c = compact_view(solver, buf)
+    idx, slots = fluid_slots(solver)
     gen = torch.Generator(device=c.device)
     gen.manual_seed(seed)
     _, w = lbm.lattice_table(Q)
-    c.normal_(generator=gen)
-    c.mul_(torch.tensor(w, dtype=c.dtype, device=c.device).view(Q, 1) * scale)
-    c[:, solver.n_fluid:] = 0
+    vals = torch.randn((Q, slots.numel()), generator=gen, dtype=torch.float64,
+                       device=c.device).to(c.dtype)
+    vals.mul_(torch.tensor(w, dtype=c.dtype, device=c.device).view(Q, 1) * scale)
+    c[:, slots] = vals
     solver.set_populations(buf)
     return dense_state(solver, buf)
 

@@ -72,13 +72,16 @@ def test_query_sizes_rejects(kw):
 @pytest.mark.parametrize("lat,prec,nx,ny,nz,nf,esize", [
     (9, lbm.LBM_FP64, 100, 50, 1, 3700, 8), (9, lbm.LBM_FP32, 100, 50, 1, 3700, 4),
     (19, lbm.LBM_FP32, 512, 512, 512, 80530637, 4), (19, lbm.LBM_FP64, 33, 7, 5, 1, 8),
-    (9, lbm.LBM_FP32, 7, 3, 1, 0, 4)])
+    (9, lbm.LBM_FP32, 7, 3, 1, 0, 4), (19, lbm.LBM_FP32, 130, 9, 7, 5000, 4)])
 def test_query_sizes_layout(lat, prec, nx, ny, nz, nf, esize):
     st, fb, wb = _status(_geom(lattice=lat, precision=prec, nx=nx, ny=ny, nz=nz, n_fluid=nf))
     assert st == lbm.LBM_OK
-    ps = max(64, (nf + 63) // 64 * 64)              # fluid nodes only, padded to 64
-    assert fb == lat * ps * esize
     nw = (nx + 63) // 64
+    S = 4 if nw >= 4 else (2 if nw >= 2 else 1)          # words per row segment
+    nsegs = ny * nz * (-(-nw // S))
+    align = 128 // esize                                  # segments start on 128 B
+    ps = max(64, (nf + (align - 1) * nsegs + 63) // 64 * 64)   # fluid slots + padding room
+    assert fb == lat * ps * esize
     assert wb >= ny * nz * (nw + 2) * 8 + ny * nz * nw * 4   # bitmap + prefix counts
 
 
