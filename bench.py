@@ -69,6 +69,34 @@ def cpu_baseline(Q, mask, tau, rho_in, rho_out, budget_s=12.0):
                       f"({dt:.1f} s wall)"}
 
 
+def kernel_source_hash():
+    """Short hash of the step kernel's sources, to tie profiled counters to them."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("kernels.h", "lattice.h", "lbm_api.hip"):
+        with open(os.path.join(ROOT, "paper_1609_09685_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic(workload):
+    """HBM bytes per launch from the committed counter summary, if it was taken
+    on the current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", f"k_step_{workload}_pmc.md")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and line.split(":")[0].strip() in ("traffic_bytes_per_launch",
+                                                              "kernel_source_sha256_16"):
+                k, v = line.split(":", 1)
+                fields[k.strip()] = v.strip()
+    if fields.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return int(fields["traffic_bytes_per_launch"])
+
+
 def copy_ceiling(gib=4, reps=5):
     """A plain device-to-device copy of `gib` GiB (torch's copy kernel), timed
     with HIP events: the achievable streaming bandwidth on this GPU, and the
@@ -157,7 +185,9 @@ def main():
                    "name": args.workload, "nodes": N, "fluid_nodes": n_fluid,
                    "mflups": round(n_fluid * args.steps / (ms / 1e3) / 1e6, 1)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": profiled_traffic(args.workload)
+                     if (args.band, args.xcd_remap) == (16, 1) else None,
                      "kernel": "k_step", "algorithmic_bytes_per_launch": alg_bytes},
     }
     out["copy_ceiling"] = copy_ceiling()
