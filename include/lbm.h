@@ -183,6 +183,76 @@ const char *lbm_last_error(void);
 /* Version of the library, e.g. "1.0.0". */
 const char *lbm_version(void);
 
+/* ------------------------------------------------------------------------
+ * Batches: many independent domains (samples of different size, porosity,
+ * tau, rho_in / rho_out) advanced together, one kernel launch per time step
+ * for all of them.  A batch is a scheduler over existing contexts: each
+ * sample is an lbm_ctx created with lbm_init (its buffers, options and state
+ * stay its own), and after every batch call each context holds exactly the
+ * state, step count and ping-pong parity that the same number of lbm_step
+ * calls would have left: per-sample results are bitwise those of running the
+ * samples one by one (same tiles, same deterministic reductions).
+ *
+ * Requirements: 1 <= n samples, all with the same lattice, precision,
+ * check_every and linear-equilibrium option, all on the batch's stream (the
+ * stream given to lbm_batch_create).  While a batch exists its contexts may
+ * still be used directly (on that stream), but their tile-order options must
+ * not change.  Convergence: after every window of K = check_every steps the
+ * flux of every running sample is reduced on the device (FP64, one launch for
+ * all samples) and read back; a sample whose residual fell below tol, whose
+ * flux is not finite, or whose next window would pass max_steps retires: its
+ * blocks are dropped from the launch table (a device table that maps every
+ * block of the launch to a sample and a block of that sample's own grid), so
+ * the remaining samples run without it.  With LBM_BATCH_OPT_GRAPH on, the
+ * K-step window and its reductions are captured once as a HIP graph and
+ * replayed.
+ */
+typedef struct lbm_batch lbm_batch;           /* opaque; host metadata only */
+
+enum {
+  LBM_BATCH_OPT_GRAPH = 1  /* 1 (default): replay each check window as a HIP graph; 0: launch */
+};
+
+/* Device work bytes for a batch of the n contexts ctxs[0..n-1] (launch and
+ * reduction tables).  The tile-order options of the contexts at this call
+ * fix the size. */
+lbm_status lbm_batch_query_sizes(int32_t n, lbm_ctx *const *ctxs, size_t *work_bytes);
+
+/* Creates a batch over ctxs[0..n-1] (the contexts are not copied: they must
+ * outlive the batch).  work: device buffer of work_bytes, 256-byte aligned;
+ * stream: hipStream_t shared by all contexts.  Uploads the tables and
+ * synchronises the stream. */
+lbm_status lbm_batch_create(lbm_batch **out, int32_t n, lbm_ctx *const *ctxs, void *work,
+                            void *stream);
+
+/* Enqueues nsteps >= 0 time steps of every sample. */
+lbm_status lbm_batch_step(lbm_batch *b, int64_t nsteps);
+
+/* lbm_run_to_steady for every sample at once, with the same tol, max_steps
+ * and check rule as the single-domain call.  Per-sample results go to
+ * caller host arrays of n entries (each may be NULL): steps_out (total steps
+ * of the context), resid_out (last residual), status_out (LBM_OK,
+ * LBM_ENOTCONV or LBM_ENONFINITE).  Returns LBM_OK if every sample
+ * converged, else the status of the first sample that did not. */
+lbm_status lbm_batch_run_to_steady(lbm_batch *b, double tol, int64_t max_steps,
+                                   int64_t *steps_out, double *resid_out,
+                                   int32_t *status_out);
+
+/* Mass flow rate of every sample's current state into q_out[n] (host). */
+lbm_status lbm_batch_flux(lbm_batch *b, double *q_out);
+
+/* Permeability of every sample into k_out[n] (host), bitwise equal to
+ * lbm_permeability of each context; status_out[n] (may be NULL) as there.
+ * Returns the first non-OK sample status, else LBM_OK. */
+lbm_status lbm_batch_permeability(lbm_batch *b, double *k_out, int32_t *status_out);
+
+/* Batch options (LBM_BATCH_OPT_*). */
+lbm_status lbm_batch_set_option(lbm_batch *b, int32_t option, int64_t value);
+
+/* Releases the batch (graphs and host tables).  Contexts and buffers are
+ * untouched.  NULL is accepted. */
+lbm_status lbm_batch_destroy(lbm_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

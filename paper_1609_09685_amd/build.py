@@ -19,7 +19,7 @@ LBM_LIB = os.path.join(PKG, "liblbm.so")
 ARCH = "gfx950"
 
 # Sources of liblbm.so, compiled together as one translation unit list.
-LBM_SOURCES = ["lbm_api.hip"]
+LBM_SOURCES = ["lbm_api.hip", "lbm_batch.hip"]
 
 HIPCC_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
@@ -44,8 +44,24 @@ def build_qsgs(verbose=False):
 
 
 def build_lbm(verbose=False):
-    srcs = [os.path.join(CSRC, s) for s in LBM_SOURCES]
-    _run(["hipcc", *HIPCC_FLAGS, f"-I{INCLUDE}", f"-I{CSRC}", "-o", LBM_LIB + ".tmp", *srcs],
+    """Compiles every source to an object in parallel, then links liblbm.so."""
+    objdir = os.path.join(PKG, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    compile_flags = [f for f in HIPCC_FLAGS if f != "-shared"]
+    procs = []
+    objs = []
+    for src in LBM_SOURCES:
+        obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
+        cmd = ["hipcc", *compile_flags, f"-I{INCLUDE}", f"-I{CSRC}", "-c", "-o", obj,
+               os.path.join(CSRC, src)]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((cmd, subprocess.Popen(cmd)))
+        objs.append(obj)
+    failed = [cmd for cmd, p in procs if p.wait() != 0]
+    if failed:
+        raise subprocess.CalledProcessError(1, failed[0])
+    _run(["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", LBM_LIB + ".tmp", *objs],
          verbose)
     os.replace(LBM_LIB + ".tmp", LBM_LIB)
     return LBM_LIB

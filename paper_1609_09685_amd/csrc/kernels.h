@@ -176,22 +176,59 @@ __device__ __forceinline__ double block1024_sum(double v) {
   return t;   // valid in thread 0
 }
 
-__global__ __launch_bounds__(1024) void k_reduce_chunks(const double* __restrict__ partial, int n,
-                                                        double* __restrict__ chunk) {
-  const int base = blockIdx.x * kChunk;
+// Sum of chunk c of n partials (fixed order) -> *out (thread 0).
+__device__ __forceinline__ void reduce_chunk(const double* __restrict__ partial, int n, int c,
+                                             double* __restrict__ out) {
+  const int base = c * kChunk;
   double v = 0.0;
   for (int j = threadIdx.x; j < kChunk; j += 1024)
     if (base + j < n) v += partial[base + j];
   const double t = block1024_sum(v);
-  if (threadIdx.x == 0) chunk[blockIdx.x] = t;
+  if (threadIdx.x == 0) *out = t;
 }
 
-__global__ __launch_bounds__(1024) void k_reduce_final(const double* __restrict__ chunk, int nchunks,
-                                                       double scale, double* __restrict__ out) {
+// Sum of nchunks chunk sums (fixed order) times scale -> *out (thread 0).
+__device__ __forceinline__ void reduce_final(const double* __restrict__ chunk, int nchunks,
+                                             double scale, double* __restrict__ out) {
   double v = 0.0;
   for (int i = threadIdx.x; i < nchunks; i += 1024) v += chunk[i];
   const double t = block1024_sum(v);
-  if (threadIdx.x == 0) out[0] = scale * t;
+  if (threadIdx.x == 0) *out = scale * t;
+}
+
+static __global__ __launch_bounds__(1024) void k_reduce_chunks(const double* __restrict__ partial, int n,
+                                                        double* __restrict__ chunk) {
+  reduce_chunk(partial, n, blockIdx.x, chunk + blockIdx.x);
+}
+
+static __global__ __launch_bounds__(1024) void k_reduce_final(const double* __restrict__ chunk, int nchunks,
+                                                       double scale, double* __restrict__ out) {
+  reduce_final(chunk, nchunks, scale, out);
+}
+
+// Flux reduction of many domains at once.  Domain d's partials, chunk sums and
+// result: part[d], chunk[d], out[d]; its chunks are blocks
+// [chunk_start[d], chunk_start[d + 1]) of the first launch and block d of the
+// second.  Same arithmetic, chunk by chunk, as the single-domain kernels.
+struct BatchReduce {
+  const double* const* part;
+  double* const* chunk;
+  const int* nparts;
+  const int* chunk_start;     // [n + 1]
+  const int* chunk_owner;     // domain of each chunk block
+  const double* scale;        // 1 / nx of each domain
+  double* out;
+};
+
+static __global__ __launch_bounds__(1024) void k_reduce_chunks_batch(BatchReduce r) {
+  const int d = r.chunk_owner[blockIdx.x];
+  const int c = blockIdx.x - r.chunk_start[d];
+  reduce_chunk(r.part[d], r.nparts[d], c, r.chunk[d] + c);
+}
+
+static __global__ __launch_bounds__(1024) void k_reduce_final_batch(BatchReduce r) {
+  const int d = blockIdx.x;
+  reduce_final(r.chunk[d], r.chunk_start[d + 1] - r.chunk_start[d], r.scale[d], r.out + d);
 }
 
 // -------------------------------------------------------------- equilibrium
@@ -519,15 +556,15 @@ __device__ __forceinline__ int logical_block(int hw, const StepArgs<T>& a) {
 // x-momentum at the index of its bitmap word, (z ny + y) nw + w, so the flux
 // does not depend on the tiling.
 template <class L, class T, bool FLUX, bool LINEAR, bool OFF32>
-__global__ __launch_bounds__(kThreads) void k_step(const StepArgs<T> a) {
+__device__ __forceinline__ void step_tile(const StepArgs<T>& a, const uint32_t hw) {
   __shared__ T out[L::Q][kThreads];
   __shared__ uint32_t seg_first[kRows], seg_count[kRows];
   int tx, ty, z;
   if (a.band > 0) {
-    const uint32_t k = blockIdx.x >> 3;
+    const uint32_t k = hw >> 3;
     const uint32_t round = a.dv_band_blocks.div(k);
     const uint32_t kk = k - round * a.dv_band_blocks.d;
-    const int bi = (int)(round * 8u + (blockIdx.x & 7u));
+    const int bi = (int)(round * 8u + (hw & 7u));
     if (bi >= a.nbands) return;   // whole block: padding band
     const uint32_t zp = a.dv_band_plane.div(kk);
     const uint32_t rem = kk - zp * a.dv_band_plane.d;
@@ -537,7 +574,7 @@ __global__ __launch_bounds__(kThreads) void k_step(const StepArgs<T> a) {
     z = (int)zp;
     if (ty >= a.tiles_y) return;   // whole block: past the last tile row
   } else {
-    const int b = logical_block(blockIdx.x, a);
+    const int b = logical_block((int)hw, a);
     if (b >= a.blocks) return;     // whole block: padding of the remapped grid
     const uint32_t r = a.dv_tiles_x.div((uint32_t)b);
     tx = b - (int)(r * (uint32_t)a.tiles_x);
@@ -600,12 +637,33 @@ __global__ __launch_bounds__(kThreads) void k_step(const StepArgs<T> a) {
   }
 }
 
+template <class L, class T, bool FLUX, bool LINEAR, bool OFF32>
+__global__ __launch_bounds__(kThreads) void k_step(const StepArgs<T> a) {
+  step_tile<L, T, FLUX, LINEAR, OFF32>(a, blockIdx.x);
+}
+
+// One time step of many domains in one launch.  Block b runs block owner[b].y
+// of the launch of domain owner[b].x, or nothing when owner[b].x < 0 (table
+// padding, and the tail left by domains that have retired).  Each domain's
+// blocks start at a multiple of 8, so block b runs on the XCD that block
+// owner[b].y of the domain's own launch would: the tile orders carry over.
+// args[2 d + flip] holds the arguments of domain d for this step (the two
+// entries of a domain differ by the ping-pong parity).
+template <class L, class T, bool FLUX, bool LINEAR, bool OFF32>
+__global__ __launch_bounds__(kThreads) void k_step_batch(const StepArgs<T>* __restrict__ args,
+                                                         const int2* __restrict__ owner, int flip) {
+  const int2 o = owner[blockIdx.x];
+  if (o.x < 0) return;   // whole block
+  const StepArgs<T> a = args[2 * o.x + flip];
+  step_tile<L, T, FLUX, LINEAR, OFF32>(a, (uint32_t)o.y);
+}
+
 // ------------------------------------------------------------ set-up kernels
 
 // Bitmap words and per-word fluid counts from the solid mask (uint8
 // [nz][ny][nx], 1 = solid).  One wave per word: the lanes ballot their nodes.
 // Also writes the two guard words of each row.
-__global__ __launch_bounds__(256) void k_pack_bits(const uint8_t* __restrict__ mask,
+static __global__ __launch_bounds__(256) void k_pack_bits(const uint8_t* __restrict__ mask,
                                                    uint64_t* __restrict__ bits,
                                                    uint32_t* __restrict__ count, int nx, int ny,
                                                    int nz, int nw) {
@@ -648,7 +706,7 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* t
   return incl - v;
 }
 
-__global__ __launch_bounds__(kScanBlock) void k_scan_local(const uint32_t* __restrict__ in,
+static __global__ __launch_bounds__(kScanBlock) void k_scan_local(const uint32_t* __restrict__ in,
                                                            uint32_t* __restrict__ out,
                                                            uint32_t* __restrict__ block_tot,
                                                            uint64_t n) {
@@ -661,7 +719,7 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_local(const uint32_t* __res
 }
 
 // One block: exclusive scan of nb block totals in place; grand total -> *sum.
-__global__ __launch_bounds__(kScanBlock) void k_scan_totals(uint32_t* __restrict__ tot, int nb,
+static __global__ __launch_bounds__(kScanBlock) void k_scan_totals(uint32_t* __restrict__ tot, int nb,
                                                             uint64_t* __restrict__ sum) {
   uint64_t carry = 0;
   for (int base = 0; base < nb; base += kScanBlock) {
@@ -675,7 +733,7 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_totals(uint32_t* __restrict
   if (threadIdx.x == 0) *sum = carry;
 }
 
-__global__ __launch_bounds__(kScanBlock) void k_scan_add(uint32_t* __restrict__ out,
+static __global__ __launch_bounds__(kScanBlock) void k_scan_add(uint32_t* __restrict__ out,
                                                          const uint32_t* __restrict__ block_tot,
                                                          uint64_t n) {
   const uint64_t i = (uint64_t)blockIdx.x * kScanBlock + threadIdx.x;
@@ -684,7 +742,7 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_add(uint32_t* __restrict__ 
 
 // Padded size of every segment (S words of a row): its fluid count rounded up
 // to `align` slots.
-__global__ __launch_bounds__(256) void k_seg_sizes(const uint32_t* __restrict__ count,
+static __global__ __launch_bounds__(256) void k_seg_sizes(const uint32_t* __restrict__ count,
                                                    uint32_t* __restrict__ seg_size, uint64_t nsegs,
                                                    int nw, int S, int segs_per_row, uint32_t align) {
   const uint64_t sg = (uint64_t)blockIdx.x * 256 + threadIdx.x;
@@ -699,7 +757,7 @@ __global__ __launch_bounds__(256) void k_seg_sizes(const uint32_t* __restrict__ 
 
 // Slot of the first fluid node of every word: the segment's first slot plus the
 // fluid nodes of the segment's earlier words.
-__global__ __launch_bounds__(256) void k_word_pfx(const uint32_t* __restrict__ count,
+static __global__ __launch_bounds__(256) void k_word_pfx(const uint32_t* __restrict__ count,
                                                   const uint32_t* __restrict__ seg_first,
                                                   uint32_t* __restrict__ pfx, uint64_t nwords, int nw,
                                                   int S, int segs_per_row) {
@@ -714,7 +772,7 @@ __global__ __launch_bounds__(256) void k_word_pfx(const uint32_t* __restrict__ c
 }
 
 // Slot of every node (x fastest), -1 for solids.
-__global__ __launch_bounds__(256) void k_slot_map(FluidMap fm, int32_t* __restrict__ map) {
+static __global__ __launch_bounds__(256) void k_slot_map(FluidMap fm, int32_t* __restrict__ map) {
   const uint64_t m = (uint64_t)blockIdx.x * 256 + threadIdx.x;
   if (m >= (uint64_t)fm.nx * fm.ny * fm.nz) return;
   const int x = (int)(m % fm.nx);

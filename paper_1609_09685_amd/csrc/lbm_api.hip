@@ -18,14 +18,16 @@
 
 #include <new>
 
-#include "kernels.h"
-#include "lbm.h"
+#include "context.h"
 
 using namespace lbm;
 
-namespace {
+namespace lbm {
+namespace host {
 
+namespace {
 thread_local char g_err[512] = "";
+}  // namespace
 
 lbm_status fail(lbm_status s, const char* fmt, ...) {
   va_list ap;
@@ -40,35 +42,12 @@ lbm_status ok() {
   return LBM_OK;
 }
 
-#define HIP_TRY(expr)                                                                   \
-  do {                                                                                  \
-    hipError_t e_ = (expr);                                                             \
-    if (e_ != hipSuccess)                                                               \
-      return fail(LBM_EHIP, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__,   \
-                  __LINE__);                                                            \
-  } while (0)
+}  // namespace host
+}  // namespace lbm
 
-size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+namespace {
 
-struct Layout {
-  int Q, D;
-  size_t esize;          // bytes per population value
-  int nw;                // bitmap words per row
-  int S;                 // words per segment (and per step tile row): 1, 2 or 4
-  int segs_per_row;      // ceil(nw / S)
-  uint32_t align;        // slots per 128 bytes
-  uint64_t rows;         // ny * nz
-  uint64_t nsegs;        // rows * segs_per_row
-  uint64_t n_fluid;
-  uint64_t ps;           // slots per direction array: room for every segment's padding
-  size_t f_bytes;
-  int scan_blocks, seg_scan_blocks;
-  size_t off_bits, off_pfx, off_count, off_scan, off_seg, off_seg_scan, off_bplane, off_partial,
-      off_scalar, work_bytes;
-  size_t bplane_one;     // elements of one parity of the boundary-plane array
-  int partials;          // capacity of the partial array
-  int chunks;            // capacity of the chunk-sum array
-};
+using namespace lbm::host;
 
 lbm_status validate_geom(const lbm_geom* g) {
   if (!g) return fail(LBM_EINVAL, "geom is NULL");
@@ -145,114 +124,12 @@ lbm_status make_layout(const lbm_geom* g, Layout* L) {
   return LBM_OK;
 }
 
-}  // namespace
-
-struct lbm_ctx {
-  lbm_geom g;
-  Layout L;
-  void* f[2];
-  const uint8_t* mask;
-  uint8_t* work;
-  hipStream_t stream;
-  double tau, rho_in, rho_out;
-  int parity;          // f[parity] holds the current state
-  int64_t steps;
-  int linear_eq;
-  int xcd_remap;
-  uint64_t n_slots;    // slots in use per direction array (fluid nodes + padding)
-  int band;            // 0 or tile rows per band (banded tile order)
-
-  uint64_t* bits() const { return (uint64_t*)(work + L.off_bits); }
-  uint32_t* pfx() const { return (uint32_t*)(work + L.off_pfx); }
-  uint32_t* count() const { return (uint32_t*)(work + L.off_count); }
-  uint32_t* scan() const { return (uint32_t*)(work + L.off_scan); }
-  uint32_t* seg() const { return (uint32_t*)(work + L.off_seg); }
-  uint32_t* seg_scan() const { return (uint32_t*)(work + L.off_seg_scan); }
-  void* bplane(int p) const { return work + L.off_bplane + (size_t)p * L.bplane_one * L.esize; }
-  double* partial() const { return (double*)(work + L.off_partial); }
-  double* scalar() const { return (double*)(work + L.off_scalar); }
-  FluidMap fmap() const {
-    FluidMap m;
-    m.bits = bits();
-    m.pfx = pfx();
-    m.nx = g.nx;
-    m.ny = g.ny;
-    m.nz = g.nz;
-    m.nw = L.nw;
-    return m;
-  }
-};
-
-namespace {
-
-// Every direction group (at most 10 arrays of ps values) spans less than
-// 4 GiB: the step kernel can use 32-bit group-relative offsets.
-bool off32_ok(const lbm_ctx* c) { return 10ull * c->L.ps * c->L.esize < (1ull << 32); }
-
-// Divisor d >= 1 for FastDiv: l = ceil(log2 d), m = 2^32 (2^l - d) / d + 1.
-FastDiv make_fastdiv(uint32_t d) {
-  FastDiv f;
-  f.d = d < 1 ? 1 : d;
-  f.l = 0;
-  while ((1ull << f.l) < f.d) ++f.l;
-  f.m = (uint32_t)(((1ull << 32) * ((1ull << f.l) - f.d)) / f.d + 1);
-  return f;
-}
-
-template <class T>
-StepArgs<T> step_args(const lbm_ctx* c) {
-  StepArgs<T> a;
-  a.src = (const T*)c->f[c->parity];
-  a.dst = (T*)c->f[c->parity ^ 1];
-  const int split = c->g.lattice == LBM_D2Q9 ? D2Q9::group_split : D3Q19::group_split;
-  a.src_g1 = a.src + (uint64_t)split * c->L.ps;
-  a.dst_g1 = a.dst + (uint64_t)split * c->L.ps;
-  a.ps_bytes = off32_ok(c) ? (uint32_t)(c->L.ps * sizeof(T)) : 0u;
-  a.bits = c->bits();
-  a.pfx = c->pfx();
-  a.bp_src = (const T*)c->bplane(c->parity);
-  a.bp_dst = (T*)c->bplane(c->parity ^ 1);
-  a.partial = c->partial();
-  a.ps = c->L.ps;
-  a.nx = c->g.nx;
-  a.ny = c->g.ny;
-  a.nz = c->g.nz;
-  a.nw = c->L.nw;
-  a.seg = c->L.S;
-  a.align = c->L.align;
-  a.tiles_x = c->L.segs_per_row;
-  const int rows = kRows / c->L.S;
-  a.tiles_y = (c->g.ny + rows - 1) / rows;
-  a.blocks = a.tiles_x * a.tiles_y * c->g.nz;
-  a.xcd_remap = c->xcd_remap;
-  // mode >= 2: chunks of (mode - 1) rows of tiles
-  a.chunk = c->xcd_remap >= 2 ? (c->xcd_remap - 1) * a.tiles_x : 1;
-  a.dv_tiles_x = make_fastdiv((uint32_t)a.tiles_x);
-  a.dv_tiles_y = make_fastdiv((uint32_t)a.tiles_y);
-  a.dv_chunk = make_fastdiv((uint32_t)a.chunk);
-  a.band = c->band;
-  a.nbands = a.band > 0 ? (a.tiles_y + a.band - 1) / a.band : 0;
-  a.dv_band_blocks = make_fastdiv((uint32_t)(a.band > 0 ? c->g.nz * a.band * a.tiles_x : 1));
-  a.dv_band_plane = make_fastdiv((uint32_t)(a.band > 0 ? a.band * a.tiles_x : 1));
-  a.omega = (T)(1.0 / c->tau);
-  a.rho0 = (T)c->g.rho0;
-  a.drho_in = (T)(c->rho_in - c->g.rho0);
-  a.drho_out = (T)(c->rho_out - c->g.rho0);
-  return a;
-}
-
-unsigned grid_1d(uint64_t n) { return (unsigned)((n + 255) / 256); }
-uint64_t n_nodes(const lbm_ctx* c) { return (uint64_t)c->g.nx * c->g.ny * c->g.nz; }
-
 template <class Lat, class T>
 lbm_status launch_steps(lbm_ctx* c, int64_t n, bool flux_last) {
   const dim3 block(kWave, kRows);
   for (int64_t s = 0; s < n; ++s) {
     StepArgs<T> a = step_args<T>(c);
-    int grid = c->xcd_remap == 0 ? a.blocks
-               : (int)align_up((size_t)a.blocks, (size_t)(c->xcd_remap == 1 ? 8 : 8 * a.chunk));
-    if (a.band > 0)   // whole rounds of 8 bands, one per XCD
-      grid = (int)(align_up((size_t)a.nbands, 8) * a.dv_band_blocks.d);
+    const int grid = step_grid(c, a);
     const bool flux = flux_last && s == n - 1;
     const int variant = (flux ? 1 : 0) | (c->linear_eq ? 2 : 0) | (off32_ok(c) ? 4 : 0);
     switch (variant) {
@@ -353,28 +230,6 @@ template <class Lat, class T> struct Bplane {
   static lbm_status run(lbm_ctx* c) { return launch_bplane<Lat, T>(c); }
 };
 
-// Reduces n partials of the last flux pass into scalar[0] and reads it back.
-lbm_status reduce_flux(lbm_ctx* c, int n, double* q) {
-  const int nch = (n + kChunk - 1) / kChunk;
-  double* chunk = c->partial() + c->L.partials;
-  k_reduce_chunks<<<nch, 1024, 0, c->stream>>>(c->partial(), n, chunk);
-  HIP_TRY(hipGetLastError());
-  k_reduce_final<<<1, 1024, 0, c->stream>>>(chunk, nch, 1.0 / c->g.nx, c->scalar());
-  HIP_TRY(hipGetLastError());
-  double h = 0.0;
-  HIP_TRY(hipMemcpyAsync(&h, c->scalar(), sizeof(double), hipMemcpyDeviceToHost, c->stream));
-  HIP_TRY(hipStreamSynchronize(c->stream));
-  *q = h;
-  return LBM_OK;
-}
-
-lbm_status current_flux(lbm_ctx* c, double* q) {
-  int n = 0;
-  lbm_status s = dispatch<Flux>(c, &n);
-  if (s != LBM_OK) return s;
-  return reduce_flux(c, n, q);
-}
-
 // Scans n counts in place (exclusive) with the three-pass scan; returns the
 // total through *total (device) - block totals go to tmp.
 lbm_status scan_in_place(lbm_ctx* c, uint32_t* data, uint64_t n, uint32_t* tmp, int nblocks,
@@ -422,13 +277,43 @@ lbm_status build_fluid_map(lbm_ctx* c) {
   return LBM_OK;
 }
 
+}  // namespace
+
+namespace lbm {
+namespace host {
+
+lbm_status flux_pass(lbm_ctx* c, int* nparts) { return dispatch<Flux>(c, nparts); }
+
+// Reduces n partials of the last flux pass into scalar[0] and reads it back.
+lbm_status reduce_flux(lbm_ctx* c, int n, double* q) {
+  const int nch = (n + kChunk - 1) / kChunk;
+  double* chunk = c->partial() + c->L.partials;
+  k_reduce_chunks<<<nch, 1024, 0, c->stream>>>(c->partial(), n, chunk);
+  HIP_TRY(hipGetLastError());
+  k_reduce_final<<<1, 1024, 0, c->stream>>>(chunk, nch, 1.0 / c->g.nx, c->scalar());
+  HIP_TRY(hipGetLastError());
+  double h = 0.0;
+  HIP_TRY(hipMemcpyAsync(&h, c->scalar(), sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  *q = h;
+  return LBM_OK;
+}
+
+lbm_status current_flux(lbm_ctx* c, double* q) {
+  int n = 0;
+  lbm_status s = flux_pass(c, &n);
+  if (s != LBM_OK) return s;
+  return reduce_flux(c, n, q);
+}
+
 double perm_from_flux(const lbm_ctx* c, double q) {
   const double nu = (c->tau - 0.5) / 3.0;
   const double L = c->g.nx + 1.0, A = (double)c->g.ny * c->g.nz;
   return nu * q * L / (A * (1.0 / 3.0) * (c->rho_in - c->rho_out));
 }
 
-}  // namespace
+}  // namespace host
+}  // namespace lbm
 
 extern "C" {
 
@@ -656,7 +541,7 @@ lbm_status lbm_destroy(lbm_ctx* c) {
   return ok();
 }
 
-const char* lbm_last_error(void) { return g_err; }
+const char* lbm_last_error(void) { return lbm::host::g_err; }
 
 const char* lbm_version(void) { return "1.0.0"; }
 

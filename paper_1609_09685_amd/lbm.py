@@ -63,6 +63,16 @@ _SIGS = {
     "lbm_steps": (_c.c_int, [_c.c_void_p, _c.POINTER(_c.c_int64)]),
     "lbm_knudsen": (_c.c_double, [_c.c_double, _c.c_int32]),
     "lbm_destroy": (_c.c_int, [_c.c_void_p]),
+    "lbm_batch_query_sizes": (_c.c_int, [_c.c_int32, _c.c_void_p, _c.POINTER(_c.c_size_t)]),
+    "lbm_batch_create": (_c.c_int, [_c.POINTER(_c.c_void_p), _c.c_int32, _c.c_void_p, _c.c_void_p,
+                                    _c.c_void_p]),
+    "lbm_batch_step": (_c.c_int, [_c.c_void_p, _c.c_int64]),
+    "lbm_batch_run_to_steady": (_c.c_int, [_c.c_void_p, _c.c_double, _c.c_int64, _c.c_void_p,
+                                           _c.c_void_p, _c.c_void_p]),
+    "lbm_batch_flux": (_c.c_int, [_c.c_void_p, _c.c_void_p]),
+    "lbm_batch_permeability": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p]),
+    "lbm_batch_set_option": (_c.c_int, [_c.c_void_p, _c.c_int32, _c.c_int64]),
+    "lbm_batch_destroy": (_c.c_int, [_c.c_void_p]),
     "lbm_last_error": (_c.c_char_p, []),
     "lbm_version": (_c.c_char_p, []),
 }
@@ -99,6 +109,7 @@ def _check(status, allow=()):
 
 LBM_OPT_XCD_REMAP, LBM_OPT_LINEAR_EQ = 1, 2
 LBM_OPT_BAND = 6
+LBM_BATCH_OPT_GRAPH = 1
 
 
 def query_sizes(lattice, nx, ny, nz, n_fluid, precision="fp32", check_every=100, rho0=1.0):
@@ -273,6 +284,94 @@ class Solver:
 
     def knudsen(self):
         return knudsen(self.tau, self.nx)
+
+    def synchronize(self):
+        self._stream.synchronize()
+
+
+class Batch:
+    """Many solvers advanced together: one step launch per time step for all.
+
+    Every per-sample result equals, bit for bit, what the same calls on each
+    Solver alone would give.  The solvers must share lattice, precision,
+    check_every, the linear-equilibrium option and the stream; they stay
+    usable on their own.
+    """
+
+    def __init__(self, solvers, graph=True):
+        import torch
+
+        self.solvers = list(solvers)
+        if not self.solvers:
+            raise ValueError("a batch needs at least one solver")
+        lib = load_library()
+        self._lib = lib
+        n = len(self.solvers)
+        self.n = n
+        self._handles = (ctypes.c_void_p * n)(*[s._h.value for s in self.solvers])
+        wb = ctypes.c_size_t(0)
+        _check(lib.lbm_batch_query_sizes(n, self._handles, ctypes.byref(wb)))
+        s0 = self.solvers[0]
+        self._stream = s0._stream
+        self._work = torch.empty(max(wb.value, 256), dtype=torch.uint8, device=s0.device)
+        h = ctypes.c_void_p(0)
+        _check(lib.lbm_batch_create(ctypes.byref(h), n, self._handles, self._work.data_ptr(),
+                                    self._stream.cuda_stream))
+        self._h = h
+        self.set_graph(graph)
+
+    @classmethod
+    def from_masks(cls, masks, taus, rho_in, rho_out, precision="fp32", check_every=100,
+                   graph=True, **kw):
+        """Solvers for masks[j] with taus[j] (scalars or per-sample sequences for rho)."""
+        n = len(masks)
+        tau = np.broadcast_to(np.asarray(taus, float), (n,))
+        rin = np.broadcast_to(np.asarray(rho_in, float), (n,))
+        rout = np.broadcast_to(np.asarray(rho_out, float), (n,))
+        solvers = [Solver(m, float(tau[j]), float(rin[j]), float(rout[j]), precision=precision,
+                          check_every=check_every, **kw) for j, m in enumerate(masks)]
+        return cls(solvers, graph=graph)
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._lib.lbm_batch_destroy(h)
+            self._h = None
+
+    __del__ = close
+
+    def set_graph(self, on=True):
+        """Replay each check window as a HIP graph (on) or launch it kernel by kernel."""
+        _check(self._lib.lbm_batch_set_option(self._h, LBM_BATCH_OPT_GRAPH, 1 if on else 0))
+
+    def step(self, n=1):
+        _check(self._lib.lbm_batch_step(self._h, int(n)))
+
+    def run_to_steady(self, tol=1e-9, max_steps=10**6):
+        """Returns (status, steps, residual) arrays, one entry per sample (status: LBM_OK,
+        LBM_ENOTCONV or LBM_ENONFINITE).  Never raises for a sample that did not converge."""
+        steps = np.zeros(self.n, np.int64)
+        resid = np.zeros(self.n)
+        status = np.zeros(self.n, np.int32)
+        st = self._lib.lbm_batch_run_to_steady(self._h, float(tol), int(max_steps),
+                                               steps.ctypes.data, resid.ctypes.data,
+                                               status.ctypes.data)
+        _check(st, allow=(LBM_ENOTCONV, LBM_ENONFINITE))
+        return status, steps, resid
+
+    def flux(self):
+        q = np.zeros(self.n)
+        _check(self._lib.lbm_batch_flux(self._h, q.ctypes.data))
+        return q
+
+    def permeability(self):
+        """(k, status) arrays; status LBM_ENOFLOW / LBM_ENONFINITE per sample where k is not a
+        permeability."""
+        k = np.zeros(self.n)
+        status = np.zeros(self.n, np.int32)
+        st = self._lib.lbm_batch_permeability(self._h, k.ctypes.data, status.ctypes.data)
+        _check(st, allow=(LBM_ENOFLOW, LBM_ENONFINITE))
+        return k, status
 
     def synchronize(self):
         self._stream.synchronize()

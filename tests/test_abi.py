@@ -146,3 +146,26 @@ def test_solver_refuses_without_gpu():
         pytest.skip("a GPU is present")
     with pytest.raises(RuntimeError):
         lbm.Solver(np.zeros((4, 8), np.uint8), 0.8, 1.001, 0.999)
+
+
+def test_batch_entry_points_validate():
+    """Batch calls reject empty or NULL arguments before touching the device."""
+    lib = lbm.load_library()
+    wb = ctypes.c_size_t(0)
+    assert lib.lbm_batch_query_sizes(0, None, ctypes.byref(wb)) == lbm.LBM_EINVAL
+    assert "n >= 1" in lib.lbm_last_error().decode()
+    assert lib.lbm_batch_query_sizes(2, None, ctypes.byref(wb)) == lbm.LBM_EINVAL
+    nulls = (ctypes.c_void_p * 2)(None, None)
+    assert lib.lbm_batch_query_sizes(2, nulls, ctypes.byref(wb)) == lbm.LBM_EINVAL
+    assert "NULL" in lib.lbm_last_error().decode()
+    h = ctypes.c_void_p(0)
+    assert lib.lbm_batch_create(ctypes.byref(h), 2, nulls, 1 << 20, None) == lbm.LBM_EINVAL
+    assert not h.value
+    assert lib.lbm_batch_create(None, 1, nulls, 1 << 20, None) == lbm.LBM_EINVAL
+    for call in (lambda: lib.lbm_batch_step(None, 1),
+                 lambda: lib.lbm_batch_run_to_steady(None, 1e-9, 10, None, None, None),
+                 lambda: lib.lbm_batch_flux(None, None),
+                 lambda: lib.lbm_batch_permeability(None, None, None),
+                 lambda: lib.lbm_batch_set_option(None, lbm.LBM_BATCH_OPT_GRAPH, 1)):
+        assert call() == lbm.LBM_EINVAL
+    assert lib.lbm_batch_destroy(None) == lbm.LBM_OK
