@@ -121,20 +121,106 @@ def copy_ceiling(gib=4, reps=5):
     return {"bytes_per_copy": moved, "ms": round(ms, 4), "gbs": round(moved / (ms / 1e3) / 1e9, 1)}
 
 
+C3_SIZES = [(400, 200), (800, 400), (1200, 600)]
+
+
+def c3_samples(n=256, seed0=1000):
+    """Batched D2Q9 workload: sample j uses seed 1000 + j for its size (uniform over
+    400x200, 800x400, 1200x600), porosity U[0.6, 0.9], tau U[0.51, 1.0] and mask."""
+    from paper_1609_09685_amd.qsgs import qsgs_2d
+    out = []
+    for j in range(n):
+        rng = np.random.default_rng(seed0 + j)
+        nx, ny = C3_SIZES[int(rng.integers(0, 3))]
+        phi = float(rng.uniform(0.6, 0.9))
+        tau = float(rng.uniform(0.51, 1.0))
+        out.append((qsgs_2d(nx, ny, phi, seed0 + j), tau, phi))
+    return out
+
+
+def bench_batch(args):
+    """256 independent D2Q9 FP32 samples advanced by one launch per step; the
+    timed region is whole check windows (K = 100 steps each, replayed as a HIP
+    graph, with the batched FP64 flux reduction and the host residual check)."""
+    import torch
+    from paper_1609_09685_amd import lbm
+    t0 = time.time()
+    samples = c3_samples(args.batch)
+    log(f"{len(samples)} masks in {time.time() - t0:.1f} s")
+    torch.cuda.set_device(0)
+    masks = [m for m, _, _ in samples]
+    taus = [t for _, t, _ in samples]
+    t0 = time.time()
+    b = lbm.Batch.from_masks(masks, taus, 1.0005, 0.9995, precision="fp32",
+                             autotune=args.autotune, graph=not args.no_graph)
+    log(f"batch of {b.n} solvers in {time.time() - t0:.1f} s")
+    N = sum(int(m.size) for m in masks)
+    n_fluid = sum(s.n_fluid for s in b.solvers)
+    K = 100
+    warm = max(K, (args.warmup + K - 1) // K * K)
+    steps = max(K, (args.steps + K - 1) // K * K)
+    b.run_to_steady(0.0, warm)          # tol 0: never converges, runs whole windows
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    b.run_to_steady(0.0, warm + steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    ms_step = ms / steps
+    # plain stepping without checks, for comparison
+    e0.record()
+    b.step(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_plain = e0.elapsed_time(e1) / steps
+    alg_bytes = n_fluid * 2 * 9 * 4 + N
+    achieved = alg_bytes / (ms_step / 1e3) / 1e9
+    out = {
+        "metric": METRIC,
+        "value": round(N * steps / (ms / 1e3) / 1e6, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1, "steps": steps, "warmup": warm,
+        "ms_per_step": round(ms_step, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"batched D2Q9 BGK fp32 deviation storage: {b.n} QSGS samples, "
+                               "sizes 400x200/800x400/1200x600, porosity U[0.6,0.9], tau "
+                               "U[0.51,1.0], rho 1.0005/0.9995; check windows of 100 steps as "
+                               "HIP graphs" + (" (off)" if args.no_graph else ""),
+                   "name": "c3_batch_fp32", "samples": b.n, "nodes": N, "fluid_nodes": n_fluid,
+                   "mflups": round(n_fluid * steps / (ms / 1e3) / 1e6, 1),
+                   "ms_per_step_without_checks": round(ms_plain, 5),
+                   "autotune": bool(args.autotune)},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "k_step_batch", "algorithmic_bytes_per_launch": alg_bytes},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="d3q19_512_fp32", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="d3q19_512_fp32",
+                    choices=sorted(WORKLOADS) + ["c3_batch_fp32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--xcd-remap", type=int, default=1)
     ap.add_argument("--band", type=int, default=16, help="banded tile order (tile rows per band; 0: off)")
+    ap.add_argument("--batch", type=int, default=256, help="samples of the batched workload")
+    ap.add_argument("--autotune", action="store_true", help="batched workload: tune tile orders")
+    ap.add_argument("--no-graph", action="store_true", help="batched workload: plain launches")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU runs are not "
                                    "part of this build", "n_gpus": args.gpus}))
         sys.exit(2)
+
+    if args.workload == "c3_batch_fp32":
+        return bench_batch(args)
 
     import torch
     from paper_1609_09685_amd import lbm

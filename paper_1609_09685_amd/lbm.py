@@ -322,14 +322,20 @@ class Batch:
 
     @classmethod
     def from_masks(cls, masks, taus, rho_in, rho_out, precision="fp32", check_every=100,
-                   graph=True, **kw):
-        """Solvers for masks[j] with taus[j] (scalars or per-sample sequences for rho)."""
+                   graph=True, autotune=False, **kw):
+        """Solvers for masks[j] with taus[j] (scalars or per-sample sequences for rho).
+        autotune: pick the step kernel's tile order per geometry class (timing only;
+        results are bitwise the same)."""
         n = len(masks)
         tau = np.broadcast_to(np.asarray(taus, float), (n,))
         rin = np.broadcast_to(np.asarray(rho_in, float), (n,))
         rout = np.broadcast_to(np.asarray(rho_out, float), (n,))
         solvers = [Solver(m, float(tau[j]), float(rin[j]), float(rout[j]), precision=precision,
                           check_every=check_every, **kw) for j, m in enumerate(masks)]
+        if autotune:
+            from . import autotune as _at
+            for s, m in zip(solvers, masks):
+                _at.apply(s, _at.tune(m, precision=precision, lattice=s.lattice))
         return cls(solvers, graph=graph)
 
     def close(self):

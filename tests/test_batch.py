@@ -151,3 +151,20 @@ def test_batch_rejects_mismatch():
         lbm.Batch([a, c])
     with pytest.raises(lbm.LBMError):
         lbm.Batch([a, a])
+
+
+def test_autotune_picks_a_candidate_and_stays_bitwise(tmp_path, monkeypatch):
+    from paper_1609_09685_amd import autotune
+    monkeypatch.setenv("LBM_AUTOTUNE_CACHE", str(tmp_path / "tune.json"))
+    masks = _masks_2d()[:3]
+    res = autotune.tune(masks[0], precision="fp32", steps=5)
+    assert (res["band"], res["xcd_remap"]) in autotune.CANDIDATES
+    assert len(res["timings"]) == len(autotune.CANDIDATES)
+    assert autotune.tune(masks[0], precision="fp32") == res      # cached
+    b = lbm.Batch.from_masks(masks, [0.8] * 3, RHO["rho_in"], RHO["rho_out"], precision="fp32",
+                             autotune=True)
+    b.step(250)
+    for j, m in enumerate(masks):
+        s = lbm.Solver(m, 0.8, precision="fp32", **RHO)
+        s.step(250)
+        assert np.array_equal(_bytes(s), _bytes(b.solvers[j]))
