@@ -19,7 +19,7 @@ LBM_LIB = os.path.join(PKG, "liblbm.so")
 ARCH = "gfx950"
 
 # Sources of liblbm.so, compiled together as one translation unit list.
-LBM_SOURCES = ["lbm_api.hip", "lbm_batch.hip"]
+LBM_SOURCES = ["lbm_api.hip", "lbm_batch.hip", "wsn_api.hip"]
 
 HIPCC_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",

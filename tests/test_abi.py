@@ -41,8 +41,10 @@ def test_every_declared_symbol_is_exported(header):
 
 
 def test_binding_covers_header():
+    from paper_1609_09685_amd import wsn
     names = declared(os.path.join(ROOT, "include", "lbm.h"))
     assert set(names) == set(lbm._SIGS)
+    assert set(declared(os.path.join(ROOT, "include", "wsn.h"))) == set(wsn._SIGS)
 
 
 def _geom(**kw):
@@ -169,3 +171,36 @@ def test_batch_entry_points_validate():
                  lambda: lib.lbm_batch_set_option(None, lbm.LBM_BATCH_OPT_GRAPH, 1)):
         assert call() == lbm.LBM_EINVAL
     assert lib.lbm_batch_destroy(None) == lbm.LBM_OK
+
+
+def test_wsn_sizes_and_validation():
+    """Network queries agree with the reference layer table; bad shapes and
+    arguments are rejected before any HIP call."""
+    from oracle import unet_ref
+    from paper_1609_09685_amd import wsn
+    L = wsn.lib()
+    npar, ab, wb = ctypes.c_int64(0), ctypes.c_size_t(0), ctypes.c_size_t(0)
+    cfg = wsn.Config(4, 32, 2, 3, 128, 256)
+    assert L.wsn_query_sizes(ctypes.byref(cfg), 8, ctypes.byref(npar), ctypes.byref(ab),
+                             ctypes.byref(wb)) == lbm.LBM_OK
+    assert npar.value == unet_ref.param_count(levels=4, base=32, in_ch=2, out_ch=3)
+    assert ab.value > 8 * 128 * 256 * 4 * 64 and wb.value > ab.value
+    for bad in [wsn.Config(0, 32, 2, 3, 128, 256), wsn.Config(4, 32, 2, 3, 100, 256),
+                wsn.Config(4, 32, 2, 3, 128, 200), wsn.Config(4, 0, 2, 3, 128, 256),
+                wsn.Config(4, 32, 2, 0, 128, 256)]:
+        assert L.wsn_query_sizes(ctypes.byref(bad), 8, None, None, None) == lbm.LBM_EINVAL
+    assert L.wsn_query_sizes(ctypes.byref(cfg), 0, None, None, None) == lbm.LBM_EINVAL
+    fake = 1 << 20
+    # width not a multiple of 16, ks not 1/3, NULL buffers
+    assert L.wsn_conv_forward(fake, fake, None, fake, 1, 8, 24, 4, 4, 3, 1, None) == lbm.LBM_EINVAL
+    assert L.wsn_conv_forward(fake, fake, None, fake, 1, 8, 32, 4, 4, 5, 1, None) == lbm.LBM_EINVAL
+    assert L.wsn_conv_forward(None, fake, None, fake, 1, 8, 32, 4, 4, 3, 1, None) == lbm.LBM_EINVAL
+    n = ctypes.c_size_t(0)
+    assert L.wsn_conv_wgrad_work(2, 16, 32, 8, 8, 3, ctypes.byref(n)) == lbm.LBM_OK and n.value > 0
+    assert L.wsn_conv_backward_weight(fake, fake, fake, None, 2, 16, 32, 8, 8, 3, fake, n.value - 1,
+                                      None) == lbm.LBM_ENOMEM
+    assert L.wsn_pool_forward(fake, fake, 1, 7, 8, 4, None) == lbm.LBM_EINVAL
+    assert L.wsn_upcat_forward(fake, fake, fake, 1, 8, 8, 0, 4, None) == lbm.LBM_EINVAL
+    assert L.wsn_adam(fake, fake, fake, fake, 10, 1e-3, 0.9, 0.999, 1e-8, 0, None) == lbm.LBM_EINVAL
+    assert L.wsn_adam(fake, fake, fake, fake, 10, 1e-3, 1.0, 0.999, 1e-8, 1, None) == lbm.LBM_EINVAL
+    assert L.wsn_mse_work(0, ctypes.byref(n)) == lbm.LBM_EINVAL
