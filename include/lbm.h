@@ -125,6 +125,15 @@ lbm_status lbm_reset(lbm_ctx *ctx, int32_t start);
  * solid nodes are ignored.  Resets the step count. */
 lbm_status lbm_set_macro(lbm_ctx *ctx, const float *rho, const float *u);
 
+/* Damps the lattice modes that change sign every step (eigenvalue -1 of the
+ * step map, e.g. momentum trapped in dead-end pores by bounce-back): n times,
+ * one time step and then the mean of the states before and after it.  Such
+ * modes carry no net mass over two steps but never decay, so a state started
+ * from fields that excite them converges to a flux offset by them; the
+ * smoothing multiplies them by (1 + lambda)/2 per pass and leaves slow modes
+ * (lambda near 1) almost unchanged.  Counts n steps. */
+lbm_status lbm_smooth(lbm_ctx *ctx, int32_t n);
+
 /* Enqueues n >= 0 time steps (stream + collide). */
 lbm_status lbm_step(lbm_ctx *ctx, int64_t n);
 

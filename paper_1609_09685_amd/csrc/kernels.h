@@ -874,6 +874,15 @@ __global__ __launch_bounds__(256) void k_macro(const T* __restrict__ f, FluidMap
 }
 
 // x-momentum of the stored populations, summed per block of 256 compact nodes.
+// a[k] = (a[k] + b[k]) / 2 over n values: the mean of two consecutive states
+// (padding slots are zero in both and stay zero).
+template <class T>
+__global__ __launch_bounds__(256) void k_mean_states(T* __restrict__ a, const T* __restrict__ b,
+                                                     uint64_t n) {
+  const uint64_t k = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  if (k < n) a[k] = T(0.5) * (a[k] + b[k]);
+}
+
 template <class L, class T>
 __global__ __launch_bounds__(256) void k_flux(const T* __restrict__ f, uint64_t n_fluid,
                                               uint64_t ps, double* __restrict__ partial) {

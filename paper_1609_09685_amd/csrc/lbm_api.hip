@@ -229,6 +229,23 @@ template <class Lat, class T> struct Macro {
 template <class Lat, class T> struct Bplane {
   static lbm_status run(lbm_ctx* c) { return launch_bplane<Lat, T>(c); }
 };
+// n times: one step, then the current state becomes the mean of the states
+// before and after that step (both ping-pong buffers), with fresh edge moments.
+template <class Lat, class T> struct Smooth {
+  static lbm_status run(lbm_ctx* c, int32_t n) {
+    const uint64_t count = (uint64_t)c->L.Q * c->L.ps;
+    for (int32_t i = 0; i < n; ++i) {
+      lbm_status s = launch_steps<Lat, T>(c, 1, false);
+      if (s != LBM_OK) return s;
+      k_mean_states<T><<<grid_1d(count), 256, 0, c->stream>>>((T*)c->f[c->parity],
+                                                               (const T*)c->f[c->parity ^ 1], count);
+      HIP_TRY(hipGetLastError());
+      s = launch_bplane<Lat, T>(c);
+      if (s != LBM_OK) return s;
+    }
+    return LBM_OK;
+  }
+};
 
 // Scans n counts in place (exclusive) with the three-pass scan; returns the
 // total through *total (device) - block totals go to tmp.
@@ -480,6 +497,13 @@ lbm_status lbm_set_populations(lbm_ctx* c, const void* src) {
   if (!c || !src) return fail(LBM_EINVAL, "NULL argument");
   HIP_TRY(hipMemcpyAsync(c->f[c->parity], src, c->L.f_bytes, hipMemcpyDeviceToDevice, c->stream));
   lbm_status s = dispatch<Bplane>(c);
+  return s == LBM_OK ? ok() : s;
+}
+
+lbm_status lbm_smooth(lbm_ctx* c, int32_t n) {
+  if (!c) return fail(LBM_EINVAL, "ctx is NULL");
+  if (n < 0) return fail(LBM_EINVAL, "n must be >= 0");
+  lbm_status s = dispatch<Smooth>(c, n);
   return s == LBM_OK ? ok() : s;
 }
 

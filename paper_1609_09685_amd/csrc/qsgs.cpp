@@ -95,6 +95,34 @@ bool percolates(const uint8_t* solid, int dim, int nx, int ny, int nz) {
   return false;
 }
 
+// Fluid nodes reachable along lattice links from a fluid node on the x = 0 or
+// x = nx - 1 plane (the inlet and outlet): open[i] = 1, else 0 (solid nodes
+// and closed pockets, which no steady through-flow can reach).
+void open_fluid(const uint8_t* solid, int dim, int nx, int ny, int nz, uint8_t* open) {
+  const int64_t N = (int64_t)nx * ny * nz;
+  std::fill(open, open + N, (uint8_t)0);
+  std::vector<int64_t> stack;
+  std::vector<Dir> dirs;
+  for (const Dir& d : neighbour_dirs(dim)) if (d.cls <= 1) dirs.push_back(d);
+  for (int z = 0; z < nz; ++z)
+    for (int y = 0; y < ny; ++y)
+      for (int x : {0, nx - 1}) {
+        const int64_t i = ((int64_t)z * ny + y) * nx + x;
+        if (!solid[i] && !open[i]) { open[i] = 1; stack.push_back(i); }
+      }
+  while (!stack.empty()) {
+    const int64_t i = stack.back();
+    stack.pop_back();
+    const int x = (int)(i % nx), y = (int)((i / nx) % ny), z = (int)(i / ((int64_t)nx * ny));
+    for (const Dir& d : dirs) {
+      const int xx = x + d.dx, yy = y + d.dy, zz = z + d.dz;
+      if (xx < 0 || xx >= nx || yy < 0 || yy >= ny || zz < 0 || zz >= nz) continue;
+      const int64_t j = ((int64_t)zz * ny + yy) * nx + xx;
+      if (!solid[j] && !open[j]) { open[j] = 1; stack.push_back(j); }
+    }
+  }
+}
+
 // One attempt.  Returns 0 on success, -2 if growth stalls before the target.
 int grow(int dim, int nx, int ny, int nz, double porosity, const double p[4],
          uint64_t sk, uint8_t* out) {
@@ -188,6 +216,14 @@ int qsgs_generate(int dim, int nx, int ny, int nz, double porosity, const double
 // 18-connected in 3D), else 0.
 int qsgs_percolates(int dim, int nx, int ny, int nz, const uint8_t* mask) {
   return percolates(mask, dim, nx, ny, nz) ? 1 : 0;
+}
+
+// open[i] = 1 for fluid nodes connected to the inlet or outlet plane (see
+// open_fluid), 0 otherwise.  Returns 0, or -1 on bad arguments.
+int qsgs_open_fluid(int dim, int nx, int ny, int nz, const uint8_t* mask, uint8_t* open) {
+  if ((dim != 2 && dim != 3) || nx < 1 || ny < 1 || nz < 1 || !mask || !open) return -1;
+  open_fluid(mask, dim, nx, ny, nz, open);
+  return 0;
 }
 
 int qsgs_num_threads(void) { return omp_get_max_threads(); }

@@ -496,4 +496,56 @@ __global__ __launch_bounds__(kBlock) void k_adam(float* __restrict__ p, const fl
   p[e] -= lr * (mm / bc1) / (sqrtf(vv / bc2) + eps);
 }
 
+// Network input from a batch of solid masks: x[b][p][0] = solid[b][p],
+// x[b][p][1] = feat[b] (the sample's scaled Knudsen number).
+__global__ __launch_bounds__(kBlock) void k_pack_input(const uint8_t* __restrict__ solid,
+                                                       const float* __restrict__ feat, int hw,
+                                                       size_t npix, float* __restrict__ x) {
+  const size_t p = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (p >= npix) return;
+  x[2 * p] = (float)solid[p];
+  x[2 * p + 1] = feat[p / hw];
+}
+
+// Solver fields (rho [b][p], u [b][2][p]) -> NHWC [b][p][3]:
+// y_k = (f_k - shift[3b + k]) * scale[3b + k].
+__global__ __launch_bounds__(kBlock) void k_fields_to_nhwc(const float* __restrict__ rho,
+                                                           const float* __restrict__ u,
+                                                           const float* __restrict__ shift,
+                                                           const float* __restrict__ scale, int hw,
+                                                           size_t npix, float* __restrict__ y) {
+  const size_t p = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (p >= npix) return;
+  const size_t b = p / hw, q = p % hw;
+  const float f[3] = {rho[p], u[(2 * b) * hw + q], u[(2 * b + 1) * hw + q]};
+  for (int k = 0; k < 3; ++k) y[3 * p + k] = (f[k] - shift[3 * b + k]) * scale[3 * b + k];
+}
+
+// NHWC [b][p][3] -> solver fields: f_k = y_k * scale[3b + k] + shift[3b + k];
+// the velocity is zero where keep_u[p] == 0 (when keep_u is given).  A
+// non-finite value anywhere in a sample's prediction is reported in bad[b].
+__global__ __launch_bounds__(kBlock) void k_nhwc_to_fields(const float* __restrict__ y,
+                                                           const float* __restrict__ shift,
+                                                           const float* __restrict__ scale,
+                                                           const uint8_t* __restrict__ keep_u,
+                                                           int hw, size_t npix,
+                                                           float* __restrict__ rho,
+                                                           float* __restrict__ u,
+                                                           int* __restrict__ bad) {
+  const size_t p = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (p >= npix) return;
+  const size_t b = p / hw, q = p % hw;
+  float f[3];
+  bool finite = true;
+  for (int k = 0; k < 3; ++k) {
+    f[k] = y[3 * p + k] * scale[3 * b + k] + shift[3 * b + k];
+    finite = finite && isfinite(f[k]);
+  }
+  if (keep_u && !keep_u[p]) f[1] = f[2] = 0.f;
+  rho[p] = f[0];
+  u[(2 * b) * hw + q] = f[1];
+  u[(2 * b + 1) * hw + q] = f[2];
+  if (!finite) bad[b] = 1;   // plain store of a flag; every writer stores the same value
+}
+
 }  // namespace wsn

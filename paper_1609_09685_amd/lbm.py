@@ -50,6 +50,7 @@ _SIGS = {
     "lbm_reset": (_c.c_int, [_c.c_void_p, _c.c_int32]),
     "lbm_set_macro": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p]),
     "lbm_step": (_c.c_int, [_c.c_void_p, _c.c_int64]),
+    "lbm_smooth": (_c.c_int, [_c.c_void_p, _c.c_int32]),
     "lbm_flux": (_c.c_int, [_c.c_void_p, _c.POINTER(_c.c_double)]),
     "lbm_permeability": (_c.c_int, [_c.c_void_p, _c.POINTER(_c.c_double)]),
     "lbm_run_to_steady": (_c.c_int, [_c.c_void_p, _c.c_double, _c.c_int64,
@@ -229,6 +230,11 @@ class Solver:
     def step(self, n=1):
         _check(self._lib.lbm_step(self._h, int(n)))
 
+    def smooth(self, n=1):
+        """n passes of: one step, then the mean of the states before and after it
+        (removes modes that alternate every step; counts n steps)."""
+        _check(self._lib.lbm_smooth(self._h, int(n)))
+
     @property
     def steps(self):
         s = ctypes.c_int64(0)
@@ -253,12 +259,20 @@ class Solver:
         _check(st, allow=() if raise_on_notconv else (LBM_ENOTCONV,))
         return st == LBM_OK, s.value, r.value
 
-    def macro(self, dtype="float64"):
-        """(rho (nz,ny,nx), u (D,nz,ny,nx)) as device tensors; solids rho0 and 0."""
+    def macro(self, dtype="float64", out=None):
+        """(rho (nz,ny,nx), u (D,nz,ny,nx)) as device tensors; solids rho0 and 0.
+        out: optional (rho, u) contiguous device tensors of those sizes to fill."""
         import torch
         td = torch.float64 if dtype == "float64" else torch.float32
-        rho = torch.empty((self.nz, self.ny, self.nx), dtype=td, device=self.device)
-        u = torch.empty((self.D, self.nz, self.ny, self.nx), dtype=td, device=self.device)
+        if out is not None:
+            rho, u = out
+            n = self.nx * self.ny * self.nz
+            if (rho.dtype != td or u.dtype != td or not rho.is_contiguous() or not u.is_contiguous()
+                    or rho.numel() != n or u.numel() != self.D * n):
+                raise ValueError("out tensors have the wrong dtype, size or layout")
+        else:
+            rho = torch.empty((self.nz, self.ny, self.nx), dtype=td, device=self.device)
+            u = torch.empty((self.D, self.nz, self.ny, self.nx), dtype=td, device=self.device)
         _check(self._lib.lbm_get_macro(self._h, rho.data_ptr(), u.data_ptr(),
                                        1 if td == torch.float64 else 0))
         return rho, u

@@ -32,6 +32,8 @@ def _load():
                                       ctypes.POINTER(ctypes.c_int)]
         lib.qsgs_percolates.restype = ctypes.c_int
         lib.qsgs_percolates.argtypes = [ctypes.c_int] * 4 + [ctypes.c_void_p]
+        lib.qsgs_open_fluid.restype = ctypes.c_int
+        lib.qsgs_open_fluid.argtypes = [ctypes.c_int] * 4 + [ctypes.c_void_p, ctypes.c_void_p]
         _lib = lib
     return _lib
 
@@ -80,3 +82,17 @@ def percolates(mask):
     m3 = m if m.ndim == 3 else m[None]
     nz, ny, nx = m3.shape
     return bool(_load().qsgs_percolates(dim, nx, ny, nz, m3.ctypes.data))
+
+
+def open_fluid(mask):
+    """uint8 array of the mask's shape: 1 for fluid nodes connected along lattice
+    links to a fluid node of the x = 0 or x = nx-1 plane, 0 elsewhere (solids and
+    closed pockets, where the steady velocity is exactly zero)."""
+    m = np.ascontiguousarray(mask, np.uint8)
+    dim = 2 if m.ndim == 2 else 3
+    m3 = m if m.ndim == 3 else m[None]
+    nz, ny, nx = m3.shape
+    out = np.zeros_like(m3)
+    if _load().qsgs_open_fluid(dim, nx, ny, nz, m3.ctypes.data, out.ctypes.data) != 0:
+        raise ValueError("bad mask")
+    return out.reshape(m.shape)

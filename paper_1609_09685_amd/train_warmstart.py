@@ -1,0 +1,100 @@
+"""Trains the warm-start network on solver steady states and measures the start
+it gives (zero vs linear-density vs learned), all on one GPU.
+
+    python -m paper_1609_09685_amd.train_warmstart --train 4096 --test 256 \
+        --epochs 20 --out warmstart.npz --report report.json
+
+Training samples use seeds 10000 + j, held-out samples 20000 + j (porosity
+U[0.6, 0.9], tau U[0.51, 1.0], 256 x 128 QSGS masks).  The parameters, the
+velocity scale and the measurements are written to --out (NumPy .npz, no
+pickles) and --report (JSON).
+"""
+import argparse
+import json
+import sys
+import time
+
+import numpy as np
+
+
+def log(msg):
+    print(f"[warmstart] {msg}", flush=True)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--train", type=int, default=4096)
+    ap.add_argument("--test", type=int, default=256)
+    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--batch", type=int, default=32)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--lr-end", type=float, default=2e-5)
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"],
+                    help="solver storage for the training data")
+    ap.add_argument("--eval-precision", default="fp64", choices=["fp32", "fp64"],
+                    help="solver storage for the start comparison")
+    ap.add_argument("--max-steps", type=int, default=200000)
+    ap.add_argument("--eval-max-steps", type=int, default=600000)
+    ap.add_argument("--chunk", type=int, default=1024, help="samples per data-generation batch")
+    ap.add_argument("--out", default=None)
+    ap.add_argument("--report", default=None)
+    args = ap.parse_args(argv)
+
+    import torch
+    from . import warmstart as ws
+
+    torch.cuda.set_device(0)
+    rep = {"args": vars(args)}
+    t0 = time.perf_counter()
+    data = ws.generate(range(10000, 10000 + args.train), chunk=args.chunk,
+                       precision=args.precision, max_steps=args.max_steps, log=log)
+    torch.cuda.synchronize()
+    rep["data_seconds"] = time.perf_counter() - t0
+    rep["train_converged"] = int(data.converged.sum())
+    rep["train_steps_median"] = float(np.median(data.steps))
+    log(f"data: {len(data)} samples in {rep['data_seconds']:.1f} s, "
+        f"{rep['train_converged']} converged")
+    u_scale = ws.u_scale_of(data)
+    rep["u_scale"] = u_scale
+    net = ws.new_network(args.batch, seed=0)
+    t0 = time.perf_counter()
+    hist = ws.train(net, data, u_scale, epochs=args.epochs, lr=args.lr, lr_end=args.lr_end, log=log)
+    torch.cuda.synchronize()
+    rep["train_seconds"] = time.perf_counter() - t0
+    rep["loss_per_epoch"] = hist
+    iters = args.epochs * (len(data) // args.batch)
+    rep["train_iterations"] = iters
+    rep["ms_per_iteration"] = 1e3 * rep["train_seconds"] / max(iters, 1)
+    log(f"training: {iters} iterations in {rep['train_seconds']:.1f} s "
+        f"({rep['ms_per_iteration']:.1f} ms each)")
+    del data
+    torch.cuda.empty_cache()
+    ev = ws.evaluate(net, range(20000, 20000 + args.test), u_scale, max_steps=args.eval_max_steps,
+                     precision=args.eval_precision, log=log)
+    rep["eval"] = ev
+    summary = {}
+    for name in ("zero", "linear", "learned"):
+        s = np.array(ev[name]["steps"])
+        summary[name] = {"steps_median": float(np.median(s)), "steps_p90": float(np.percentile(s, 90)),
+                         "steps_total": int(s.sum()), "seconds": ev[name]["seconds"],
+                         "converged": int(sum(1 for v in ev[name]["status"] if v == 0))}
+    for name in ("linear", "learned"):
+        summary[name]["k_rel_err_max"] = ev[name]["k_rel_err_max"]
+    summary["learned"]["fallbacks"] = ev["learned"]["fallbacks"]
+    for name in ("zero", "linear", "learned"):
+        summary[name]["reruns"] = ev[name]["reruns"]
+    z, l = np.array(ev["zero"]["steps"]), np.array(ev["learned"]["steps"])
+    summary["learned"]["step_ratio_median"] = float(np.median(l / z))
+    rep["summary"] = summary
+    log(json.dumps(summary))
+    if args.out:
+        np.savez(args.out, params=net.params.cpu().numpy(), u_scale=np.array(u_scale),
+                 levels=np.array(4), base=np.array(32))
+    if args.report:
+        with open(args.report, "w") as fh:
+            json.dump(rep, fh, indent=1)
+    return rep
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:])

@@ -1,0 +1,303 @@
+"""Learned warm start for the permeability solver.
+
+A small U-Net (the HIP network of ``wsn``) maps a 2D solid mask and the
+Knudsen number Kn = sqrt(pi/6)(tau - 1/2)/Nx (the paper's discussion of Fig.
+2) to the steady density and velocity fields; the solver then starts from the
+equilibrium populations of that prediction and runs, as always, to the same
+flux residual.  The network only changes how many steps that takes: the
+converged answer is the solver's.
+
+Steps, all on the GPU through the library's entry points:
+
+1. data: batched solver runs (``lbm.Batch``) of random QSGS masks to the
+   steady state, fields read back with ``lbm_get_macro`` and normalised by
+   Stokes linearity (``wsn_fields_to_nhwc``):
+       rho' = (rho - rho_bar) / drho,   u' = u nu L / (c_s^2 drho) / U_SCALE,
+   where L = Nx + 1 and drho = rho_in - rho_out: in the Stokes regime both are
+   independent of drho, and u' is a local permeability (Darcy's law);
+2. training: masked MSE over fluid nodes, Adam (``wsn_*`` kernels);
+3. start: prediction -> fields (``wsn_nhwc_to_fields``, velocity zero in
+   closed pockets) -> ``lbm_set_macro`` -> ``lbm_smooth`` (removes the modes
+   that alternate every step and never decay, which an imperfect field
+   excites at dead-end pores); a sample whose prediction is not finite starts
+   from rest instead, and one whose converged state still alternates from
+   step to step is rerun from rest (``run_checked``).
+"""
+import time
+
+import numpy as np
+
+from . import lbm, wsn
+from .qsgs import qsgs_2d
+
+NX, NY = 256, 128
+RHO_IN, RHO_OUT = 1.0005, 0.9995
+KN_SCALE = 1e-3          # network input: Kn / KN_SCALE
+CS2 = 1.0 / 3.0
+
+
+def sample(seed, nx=NX, ny=NY):
+    """(mask, tau, porosity) of one sample: porosity U[0.6, 0.9], tau U[0.51, 1.0]
+    from a generator seeded with `seed`, QSGS mask with the same seed."""
+    rng = np.random.default_rng(seed)
+    phi = float(rng.uniform(0.6, 0.9))
+    tau = float(rng.uniform(0.51, 1.0))
+    return qsgs_2d(nx, ny, phi, seed), tau, phi
+
+
+def features(taus, nx):
+    return np.array([lbm.knudsen(t, nx) / KN_SCALE for t in taus], np.float32)
+
+
+def target_maps(taus, nx, u_scale, rho_in=RHO_IN, rho_out=RHO_OUT):
+    """Per-sample (shift, scale) [B, 3] for fields -> normalised targets, and for
+    the inverse direction."""
+    taus = np.asarray(taus, float)
+    drho = rho_in - rho_out
+    rho_bar = 0.5 * (rho_in + rho_out)
+    nu = (taus - 0.5) / 3.0
+    uf = nu * (nx + 1) / (CS2 * drho) / u_scale          # u -> u'
+    shift = np.zeros((len(taus), 3))
+    shift[:, 0] = rho_bar
+    fwd = np.stack([np.full_like(uf, 1.0 / drho), uf, uf], 1)
+    inv = 1.0 / fwd
+    return shift.astype(np.float32), fwd.astype(np.float32), inv.astype(np.float32)
+
+
+def _dev(a):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a)).cuda()
+
+
+class Dataset:
+    """Device tensors of n samples: x [n,H,W,2], fields rho [n,H,W], u [n,2,H,W],
+    solid [n,H,W] uint8, and per-sample tau, steps, k, converged."""
+
+    def __init__(self, x, rho, u, solid, taus, steps, k, converged, seeds):
+        self.x, self.rho, self.u, self.solid = x, rho, u, solid
+        self.taus, self.steps, self.k = np.asarray(taus), np.asarray(steps), np.asarray(k)
+        self.converged, self.seeds = np.asarray(converged), np.asarray(seeds)
+
+    def __len__(self):
+        return len(self.taus)
+
+    def targets(self, u_scale):
+        shift, fwd, _ = target_maps(self.taus, self.x.shape[2], u_scale)
+        return wsn.fields_to_nhwc(self.rho, self.u, _dev(shift), _dev(fwd))
+
+
+def solve(masks, taus, precision="fp32", tol=1e-9, max_steps=400000, starts=None, graph=True):
+    """Runs the samples to the steady state in one batch.  starts[j]: None (rest,
+    uniform density) or (rho, u) device tensors for lbm_set_macro.  Returns
+    (batch, status, steps, resid, seconds)."""
+    import torch
+    b = lbm.Batch.from_masks(masks, taus, RHO_IN, RHO_OUT, precision=precision, graph=graph)
+    if starts is not None:
+        for s, st in zip(b.solvers, starts):
+            if st is not None:
+                s.set_macro(*st)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    status, steps, resid = b.run_to_steady(tol, max_steps)
+    torch.cuda.synchronize()
+    return b, status, steps, resid, time.perf_counter() - t0
+
+
+def generate(seeds, chunk=1024, precision="fp32", tol=1e-9, max_steps=400000, log=None):
+    """Steady states of the samples `seeds` (zero-velocity start), in batches of
+    `chunk` samples.  Samples that do not converge are kept and flagged."""
+    import torch
+    seeds = list(seeds)
+    n = len(seeds)
+    x = torch.empty((n, NY, NX, 2), dtype=torch.float32, device="cuda")
+    rho = torch.empty((n, NY, NX), dtype=torch.float32, device="cuda")
+    u = torch.empty((n, 2, NY, NX), dtype=torch.float32, device="cuda")
+    solid = torch.empty((n, NY, NX), dtype=torch.uint8, device="cuda")
+    taus, steps, ks, conv = np.zeros(n), np.zeros(n, np.int64), np.zeros(n), np.zeros(n, bool)
+    for c0 in range(0, n, chunk):
+        part = seeds[c0:c0 + chunk]
+        smp = [sample(s) for s in part]
+        masks = [m for m, _, _ in smp]
+        tt = [t for _, t, _ in smp]
+        b, status, st, _, sec = solve(masks, tt, precision, tol, max_steps)
+        k, _ = b.permeability()
+        for j, s in enumerate(b.solvers):
+            s.macro("float32", out=(rho[c0 + j], u[c0 + j]))
+        m = len(part)
+        solid[c0:c0 + m] = torch.as_tensor(np.stack(masks)).cuda()
+        wsn.pack_input(solid[c0:c0 + m], _dev(features(tt, NX)), out=x[c0:c0 + m])
+        taus[c0:c0 + m], steps[c0:c0 + m], ks[c0:c0 + m] = tt, st, k
+        conv[c0:c0 + m] = status == lbm.LBM_OK
+        torch.cuda.synchronize()
+        b.close()
+        del b
+        if log:
+            log(f"samples {c0}..{c0 + m - 1}: {int(conv[c0:c0 + m].sum())}/{m} converged, steps "
+                f"median {int(np.median(st))} max {int(st.max())}, {sec:.1f} s")
+    return Dataset(x, rho, u, solid, taus, steps, ks, conv, seeds)
+
+
+def u_scale_of(data, sample_count=64):
+    """RMS of u nu L / (c_s^2 drho) over the fluid nodes of the first samples."""
+    shift, fwd, _ = target_maps(data.taus[:sample_count], NX, 1.0)
+    y = wsn.fields_to_nhwc(data.rho[:sample_count].contiguous(), data.u[:sample_count].contiguous(),
+                           _dev(shift), _dev(fwd)).cpu().numpy()
+    fluid = data.solid[:sample_count].cpu().numpy() == 0
+    return float(np.sqrt((y[..., 1:][fluid] ** 2).mean()))
+
+
+def new_network(batch, seed=0, levels=4, base=32):
+    """A U-Net with He-normal initial weights drawn from a seeded NumPy generator."""
+    shapes = []
+    ch = [base * 2 ** l for l in range(levels)]
+    cin = 2
+    for l in range(levels):
+        shapes += [(3, cin, ch[l]), (3, ch[l], ch[l])]
+        cin = ch[l]
+    for l in range(levels - 2, -1, -1):
+        shapes += [(3, ch[l + 1] + ch[l], ch[l]), (3, ch[l], ch[l])]
+    shapes.append((1, ch[0], 3))
+    rng = np.random.default_rng(seed)
+    parts = []
+    for ks, ci, co in shapes:
+        parts.append(rng.standard_normal(ks * ks * ci * co) * np.sqrt(2.0 / (ks * ks * ci)))
+        parts.append(np.zeros(co))
+    return wsn.WarmStartNet(np.concatenate(parts).astype(np.float32), batch, levels=levels,
+                            base=base, height=NY, width=NX)
+
+
+def train(net, data, u_scale, epochs=20, lr=1e-3, lr_end=1e-5, seed=0, log=None):
+    """Adam on the masked MSE; minibatches are contiguous slices of the data in a
+    shuffled order per epoch, learning rate decayed geometrically to lr_end.
+    Returns the mean loss of every epoch."""
+    import torch
+    B = net.batch
+    y_all = data.targets(u_scale)
+    nb = len(data) // B
+    rng = np.random.default_rng(seed)
+    total = epochs * nb
+    hist = []
+    it = 0
+    for ep in range(epochs):
+        losses = []
+        for i in rng.permutation(nb):
+            sl = slice(i * B, (i + 1) * B)
+            rate = lr * (lr_end / lr) ** (it / max(total - 1, 1))
+            losses.append(net.train_step(data.x[sl], y_all[sl], data.solid[sl], rate))
+            it += 1
+        ep_loss = float(torch.stack(losses).mean().item())
+        hist.append(ep_loss)
+        if log:
+            log(f"epoch {ep + 1}/{epochs}: loss {ep_loss:.4e}")
+    return hist
+
+
+def predict(net, masks, taus, u_scale):
+    """Fields (rho [B,H,W], u [B,2,H,W]) and the non-finite flags of the network's
+    prediction for the samples (any number; run in chunks of the net's batch).
+    The velocity is set to zero in fluid pockets that no path along lattice
+    links joins to the inlet or outlet: the steady flow there is exactly zero,
+    and a closed pocket keeps whatever momentum it starts with."""
+    import torch
+    from .qsgs import open_fluid
+    n = len(masks)
+    rho = torch.empty((n, NY, NX), dtype=torch.float32, device="cuda")
+    u = torch.empty((n, 2, NY, NX), dtype=torch.float32, device="cuda")
+    bad = torch.empty(n, dtype=torch.int32, device="cuda")
+    shift, _, inv = target_maps(taus, NX, u_scale)
+    for c0 in range(0, n, net.batch):
+        m = min(net.batch, n - c0)
+        solid = _dev(np.stack(masks[c0:c0 + m]).astype(np.uint8))
+        keep = _dev(np.stack([open_fluid(mk) for mk in masks[c0:c0 + m]]))
+        x = wsn.pack_input(solid, _dev(features(taus[c0:c0 + m], NX)))
+        y = net.infer(x)
+        wsn.nhwc_to_fields(y, _dev(shift[c0:c0 + m]), _dev(inv[c0:c0 + m]), keep_u=keep,
+                           out=(rho[c0:c0 + m], u[c0:c0 + m], bad[c0:c0 + m]))
+    return rho, u, bad
+
+
+ONE_STEP_TOL = 1e-6   # relative flux change over one step that marks a period-2 mode
+SMOOTH_PASSES = 4     # lbm_smooth passes after a start from predicted fields
+
+
+def run_checked(masks, taus, start, precision, tol, max_steps, rerun_failed=True):
+    """Runs the samples in one batch from `start(batch)` (which sets every
+    solver's initial state and may take time of its own) to the flux residual
+    tol, then checks one more step: a converged state whose flux changes by
+    more than ONE_STEP_TOL in a single step carries a period-2 oscillation
+    that the residual, taken every K (even) steps, cannot see; such samples
+    are rerun from the zero-velocity start, their steps added.  Returns a dict
+    with per-sample status, steps, k, the rerun flags and the wall time."""
+    import torch
+    b = lbm.Batch.from_masks(masks, taus, RHO_IN, RHO_OUT, precision=precision)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start(b)
+    status, steps, _ = b.run_to_steady(tol, max_steps)
+    k, _ = b.permeability()
+    q0 = b.flux()
+    b.step(1)
+    q1 = b.flux()
+    one = np.abs(q1 - q0) / np.abs(q0)
+    flagged = (status == lbm.LBM_OK) & (one > ONE_STEP_TOL)
+    rerun = flagged & rerun_failed
+    steps = steps + 1
+    if rerun.any():
+        idx = np.nonzero(rerun)[0]
+        for j in idx:
+            b.solvers[j].reset("uniform")
+        b2 = lbm.Batch([b.solvers[j] for j in idx])
+        st2, steps2, _ = b2.run_to_steady(tol, max_steps)
+        k2, _ = b2.permeability()
+        status[idx], steps[idx], k[idx] = st2, steps[idx] + steps2, k2
+        b2.close()
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    b.close()
+    return dict(status=status.tolist(), steps=steps.tolist(), k=k.tolist(), seconds=sec,
+                one_step_change=one.tolist(), flagged=int(flagged.sum()), reruns=int(rerun.sum()))
+
+
+def evaluate(net, seeds, u_scale, tol=1e-9, max_steps=600000, precision="fp64", log=None):
+    """Zero, linear-density and learned starts on the samples `seeds`: per-sample
+    steps and permeabilities, and the wall time of each batch job (the learned
+    start's includes inference, the field conversion and lbm_set_macro)."""
+    smp = [sample(s) for s in seeds]
+    masks = [m for m, _, _ in smp]
+    taus = [t for _, t, _ in smp]
+    out = {"seeds": list(seeds), "tau": taus, "precision": precision}
+
+    def zero(b):
+        pass
+
+    def linear(b):
+        for s in b.solvers:
+            s.reset("linear")
+
+    info = {}
+
+    def learned(b):
+        rho, u, bad = predict(net, masks, taus, u_scale)
+        badh = bad.cpu().numpy()
+        for j, s in enumerate(b.solvers):
+            if badh[j]:
+                s.reset("uniform")                 # fallback: the plain start
+            else:
+                s.set_macro(rho[j], u[j])
+                s.smooth(SMOOTH_PASSES)
+        info["fallbacks"] = int(badh.sum())
+
+    # the zero start is the plain method: judged by the same check, never rerun
+    for name, fn in (("zero", zero), ("linear", linear), ("learned", learned)):
+        out[name] = run_checked(masks, taus, fn, precision, tol, max_steps,
+                                rerun_failed=name != "zero")
+    out["learned"]["fallbacks"] = info["fallbacks"]
+    kz = np.array(out["zero"]["k"])
+    for name in ("linear", "learned"):
+        out[name]["k_rel_err_max"] = float(np.max(np.abs(np.array(out[name]["k"]) - kz) / np.abs(kz)))
+    if log:
+        for name in ("zero", "linear", "learned"):
+            s = np.array(out[name]["steps"])
+            log(f"{name:8s}: steps median {np.median(s):.0f} p90 {np.percentile(s, 90):.0f}, "
+                f"{out[name]['seconds']:.2f} s, reruns {out[name]['reruns']}")
+    return out

@@ -42,6 +42,9 @@ _SIGS = {
     "wsn_pool_backward": (_c.c_int, [_p, _p, _p, _p, _i, _i, _i, _i, _p]),
     "wsn_upcat_forward": (_c.c_int, [_p, _p, _p, _i, _i, _i, _i, _i, _p]),
     "wsn_upcat_backward": (_c.c_int, [_p, _p, _p, _i, _i, _i, _i, _i, _p]),
+    "wsn_pack_input": (_c.c_int, [_p, _p, _i, _i, _i, _p, _p]),
+    "wsn_fields_to_nhwc": (_c.c_int, [_p, _p, _p, _p, _i, _i, _i, _p, _p]),
+    "wsn_nhwc_to_fields": (_c.c_int, [_p, _p, _p, _p, _i, _i, _i, _p, _p, _p, _p]),
 }
 
 _lib = None
@@ -179,6 +182,52 @@ def adam(p, g, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):
                           float(lr), float(b1), float(b2), float(eps), int(t), _stream(p.device)))
 
 
+def pack_input(solid, feat, out=None):
+    """solid uint8 [B,H,W], feat float32 [B] -> x [B,H,W,2] (into `out` if given)."""
+    import torch
+    B, H, W = solid.shape
+    x = out if out is not None else torch.empty((B, H, W, 2), dtype=torch.float32,
+                                                device=solid.device)
+    if tuple(x.shape) != (B, H, W, 2):
+        raise ValueError("out has the wrong shape")
+    _check(lib().wsn_pack_input(_ptr(solid), _ptr(_f32(feat)), B, H, W, _ptr(x),
+                                _stream(solid.device)))
+    return x
+
+
+def fields_to_nhwc(rho, u, shift, scale):
+    """rho [B,H,W], u [B,2,H,W] -> y [B,H,W,3] = (f - shift) * scale (per sample, channel)."""
+    import torch
+    B, H, W = rho.shape
+    y = torch.empty((B, H, W, 3), dtype=torch.float32, device=rho.device)
+    _check(lib().wsn_fields_to_nhwc(_ptr(_f32(rho)), _ptr(_f32(u)), _ptr(_f32(shift)),
+                                    _ptr(_f32(scale)), B, H, W, _ptr(y), _stream(rho.device)))
+    return y
+
+
+def nhwc_to_fields(y, shift, scale, keep_u=None, out=None):
+    """y [B,H,W,3] -> (rho [B,H,W], u [B,2,H,W], bad [B] int32) with f = y * scale + shift,
+    u = 0 where keep_u (uint8 [B,H,W]) is 0, into the tensors of `out` if given."""
+    import torch
+    B, H, W, _ = y.shape
+    if out is not None:
+        rho, u, bad = out
+        if (tuple(rho.shape) != (B, H, W) or tuple(u.shape) != (B, 2, H, W) or
+                tuple(bad.shape) != (B,) or bad.dtype != torch.int32 or not bad.is_contiguous()):
+            raise ValueError("out tensors have the wrong shape")
+    else:
+        rho = torch.empty((B, H, W), dtype=torch.float32, device=y.device)
+        u = torch.empty((B, 2, H, W), dtype=torch.float32, device=y.device)
+        bad = torch.empty(B, dtype=torch.int32, device=y.device)
+    if keep_u is not None and (keep_u.dtype != torch.uint8 or tuple(keep_u.shape) != (B, H, W)
+                               or not keep_u.is_contiguous()):
+        raise ValueError("keep_u must be a contiguous uint8 [B,H,W] tensor")
+    _check(lib().wsn_nhwc_to_fields(_ptr(_f32(y)), _ptr(_f32(shift)), _ptr(_f32(scale)),
+                                    _ptr(keep_u), B, H, W, _ptr(rho), _ptr(u), _ptr(bad),
+                                    _stream(y.device)))
+    return rho, u, bad
+
+
 # ---------------------------------------------------------------- network
 
 class WarmStartNet:
@@ -222,6 +271,17 @@ class WarmStartNet:
         _check(lib().wsn_forward(ctypes.byref(self.cfg), self.batch, _ptr(self.params),
                                  _ptr(_f32(x)), _ptr(y), _ptr(self.act), _stream(self.device)))
         self._x = x
+        return y
+
+    def infer(self, x):
+        """Forward pass of any batch of at most `batch` inputs; returns y."""
+        import torch
+        B = x.shape[0]
+        if B > self.batch or tuple(x.shape[1:]) != self.shape_in[1:]:
+            raise ValueError(f"input shape {tuple(x.shape)} does not fit {self.shape_in}")
+        y = torch.empty((B,) + self.shape_out[1:], dtype=torch.float32, device=self.device)
+        _check(lib().wsn_forward(ctypes.byref(self.cfg), B, _ptr(self.params), _ptr(_f32(x)),
+                                 _ptr(y), _ptr(self.act), _stream(self.device)))
         return y
 
     def backward(self, dy):

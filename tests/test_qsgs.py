@@ -70,3 +70,30 @@ def test_invalid_arguments():
         qsgs.qsgs_2d(0, 10, 0.7, 0)
     with pytest.raises(qsgs.QSGSError):
         qsgs.qsgs_2d(10, 10, 1.5, 0)
+
+
+@pytest.mark.parametrize("shape,phi,seed", [((60, 90), 0.6, 3), ((40, 50), 0.75, 8),
+                                            ((12, 20, 30), 0.6, 2)])
+def test_open_fluid_matches_connected_components(shape, phi, seed):
+    """Fluid connected to the inlet/outlet planes equals the union of the
+    lattice-connected components (8 in 2D, 18 in 3D) touching x = 0 or nx-1."""
+    import scipy.ndimage as ndi
+    from paper_1609_09685_amd.qsgs import open_fluid, qsgs_2d, qsgs_3d
+    if len(shape) == 2:
+        m = qsgs_2d(shape[1], shape[0], phi, seed)
+        st = np.ones((3, 3))
+    else:
+        m = qsgs_3d(shape[2], shape[1], shape[0], phi, seed)
+        st = ndi.generate_binary_structure(3, 2)     # faces + edges
+    lab, _ = ndi.label(m == 0, structure=st)
+    ids = set(np.unique(lab[..., 0])) | set(np.unique(lab[..., -1]))
+    ids.discard(0)
+    ref = np.isin(lab, list(ids)).astype(np.uint8)
+    got = open_fluid(m)
+    assert np.array_equal(got, ref)
+    # a closed pocket is excluded
+    m2 = np.zeros((5, 8), np.uint8)
+    m2[1:4, 3:6] = 1
+    m2[2, 4] = 0
+    o = open_fluid(m2)
+    assert o[2, 4] == 0 and o[0, 0] == 1 and o.sum() == (m2 == 0).sum() - 1
