@@ -50,10 +50,10 @@ def main(argv=None):
                        precision=args.precision, max_steps=args.max_steps, log=log)
     torch.cuda.synchronize()
     rep["data_seconds"] = time.perf_counter() - t0
-    rep["train_converged"] = int(data.converged.sum())
+    rep["train_samples_kept"] = len(data)
+    rep["train_samples_dropped"] = data.dropped
     rep["train_steps_median"] = float(np.median(data.steps))
-    log(f"data: {len(data)} samples in {rep['data_seconds']:.1f} s, "
-        f"{rep['train_converged']} converged")
+    log(f"data: {len(data)} samples kept in {rep['data_seconds']:.1f} s, dropped {data.dropped}")
     u_scale = ws.u_scale_of(data)
     rep["u_scale"] = u_scale
     net = ws.new_network(args.batch, seed=0)

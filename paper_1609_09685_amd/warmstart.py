@@ -105,7 +105,8 @@ def solve(masks, taus, precision="fp32", tol=1e-9, max_steps=400000, starts=None
 
 def generate(seeds, chunk=1024, precision="fp32", tol=1e-9, max_steps=400000, log=None):
     """Steady states of the samples `seeds` (zero-velocity start), in batches of
-    `chunk` samples.  Samples that do not converge are kept and flagged."""
+    `chunk` samples.  Only samples that reach the residual are kept (packed in
+    seed order); the others are counted in `dropped`."""
     import torch
     seeds = list(seeds)
     n = len(seeds)
@@ -113,28 +114,37 @@ def generate(seeds, chunk=1024, precision="fp32", tol=1e-9, max_steps=400000, lo
     rho = torch.empty((n, NY, NX), dtype=torch.float32, device="cuda")
     u = torch.empty((n, 2, NY, NX), dtype=torch.float32, device="cuda")
     solid = torch.empty((n, NY, NX), dtype=torch.uint8, device="cuda")
-    taus, steps, ks, conv = np.zeros(n), np.zeros(n, np.int64), np.zeros(n), np.zeros(n, bool)
+    taus, steps, ks, kept = [], [], [], []
+    dropped = {"not_converged": 0, "non_finite": 0}
     for c0 in range(0, n, chunk):
         part = seeds[c0:c0 + chunk]
         smp = [sample(s) for s in part]
-        masks = [m for m, _, _ in smp]
-        tt = [t for _, t, _ in smp]
-        b, status, st, _, sec = solve(masks, tt, precision, tol, max_steps)
-        k, _ = b.permeability()
+        b, status, st, _, sec = solve([m for m, _, _ in smp], [t for _, t, _ in smp], precision,
+                                      tol, max_steps)
+        k, kst = b.permeability()
         for j, s in enumerate(b.solvers):
-            s.macro("float32", out=(rho[c0 + j], u[c0 + j]))
-        m = len(part)
-        solid[c0:c0 + m] = torch.as_tensor(np.stack(masks)).cuda()
-        wsn.pack_input(solid[c0:c0 + m], _dev(features(tt, NX)), out=x[c0:c0 + m])
-        taus[c0:c0 + m], steps[c0:c0 + m], ks[c0:c0 + m] = tt, st, k
-        conv[c0:c0 + m] = status == lbm.LBM_OK
+            if status[j] != lbm.LBM_OK or kst[j] != lbm.LBM_OK:
+                dropped["non_finite" if status[j] == lbm.LBM_ENONFINITE else "not_converged"] += 1
+                continue
+            i = len(kept)
+            s.macro("float32", out=(rho[i], u[i]))
+            solid[i] = torch.as_tensor(smp[j][0]).cuda()
+            kept.append(part[j])
+            taus.append(smp[j][1])
+            steps.append(int(st[j]))
+            ks.append(float(k[j]))
         torch.cuda.synchronize()
         b.close()
         del b
         if log:
-            log(f"samples {c0}..{c0 + m - 1}: {int(conv[c0:c0 + m].sum())}/{m} converged, steps "
-                f"median {int(np.median(st))} max {int(st.max())}, {sec:.1f} s")
-    return Dataset(x, rho, u, solid, taus, steps, ks, conv, seeds)
+            log(f"samples {c0}..{c0 + len(part) - 1}: {int((status == lbm.LBM_OK).sum())}/"
+                f"{len(part)} converged, steps median {int(np.median(st))} max {int(st.max())}, "
+                f"{sec:.1f} s")
+    m = len(kept)
+    wsn.pack_input(solid[:m], _dev(features(taus, NX)), out=x[:m])
+    d = Dataset(x[:m], rho[:m], u[:m], solid[:m], taus, steps, ks, np.ones(m, bool), kept)
+    d.dropped = dropped
+    return d
 
 
 def u_scale_of(data, sample_count=64):
