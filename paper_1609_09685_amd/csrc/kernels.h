@@ -615,7 +615,9 @@ __device__ __forceinline__ void step_tile(const StepArgs<T>& a, const uint32_t h
     }
   }
   __syncthreads();
-  // whole-line stores: thread t writes position t of its row's segment
+  // whole-line stores: thread t writes position t of its row's segment; the
+  // next step reads them from HBM anyway, so they bypass the caches
+  // (nontemporal), which pays now that no store leaves a partial line
   const int t = wave * kWave + lane;
   const int jj = t / (S * kWave);
   const uint32_t r = (uint32_t)(t - jj * S * kWave);
@@ -629,9 +631,10 @@ __device__ __forceinline__ void step_tile(const StepArgs<T>& a, const uint32_t h
       if constexpr (OFF32) {
         constexpr int f = q < L::group_split ? 0 : L::group_split;
         char* base = q < L::group_split ? (char*)a.dst : (char*)a.dst_g1;
-        *(T*)(base + (slot * (uint32_t)sizeof(T) + (uint32_t)(q - f) * a.ps_bytes)) = v;
+        __builtin_nontemporal_store(
+            v, (T*)(base + (slot * (uint32_t)sizeof(T) + (uint32_t)(q - f) * a.ps_bytes)));
       } else {
-        a.dst[(uint64_t)q * a.ps + slot] = v;
+        __builtin_nontemporal_store(v, a.dst + ((uint64_t)q * a.ps + slot));
       }
     });
   }
