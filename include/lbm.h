@@ -241,11 +241,14 @@ lbm_status lbm_batch_step(lbm_batch *b, int64_t nsteps);
  * and check rule as the single-domain call.  Per-sample results go to
  * caller host arrays of n entries (each may be NULL): steps_out (total steps
  * of the context), resid_out (last residual), status_out (LBM_OK,
- * LBM_ENOTCONV or LBM_ENONFINITE).  Returns LBM_OK if every sample
- * converged, else the status of the first sample that did not. */
+ * LBM_ENOTCONV or LBM_ENONFINITE).  q_log (host, may be NULL when
+ * log_windows is 0): the flux of sample d after window w of this call at
+ * q_log[w * n + d] for the first log_windows windows, NaN once the sample
+ * has retired.  Returns LBM_OK if every sample converged, else the status of
+ * the first sample that did not. */
 lbm_status lbm_batch_run_to_steady(lbm_batch *b, double tol, int64_t max_steps,
                                    int64_t *steps_out, double *resid_out,
-                                   int32_t *status_out);
+                                   int32_t *status_out, double *q_log, int64_t log_windows);
 
 /* Mass flow rate of every sample's current state into q_out[n] (host). */
 lbm_status lbm_batch_flux(lbm_batch *b, double *q_out);

@@ -137,18 +137,21 @@ lbm_status wsn_pack_input(const uint8_t *solid, const float *feat, int32_t batch
 
 /* Solver fields of a batch (rho [batch][height][width] and u [batch][2][height][width],
  * the layout of lbm_get_macro per sample) into NHWC [batch][height][width][3]:
- * y_k = (f_k - shift[3 b + k]) * scale[3 b + k], f = (rho, u_x, u_y). */
+ * y_k = (f_k - shift[3 b + k] - slope[3 b + k] (x + 1)) * scale[3 b + k],
+ * f = (rho, u_x, u_y), x the column; slope may be NULL (no term). */
 lbm_status wsn_fields_to_nhwc(const float *rho, const float *u, const float *shift,
-                              const float *scale, int32_t batch, int32_t height, int32_t width,
-                              float *y, void *stream);
+                              const float *slope, const float *scale, int32_t batch,
+                              int32_t height, int32_t width, float *y, void *stream);
 
-/* The inverse direction: f_k = y_k * scale[3 b + k] + shift[3 b + k], into the
- * layout of lbm_set_macro; u = 0 wherever keep_u[b][p] == 0 (keep_u: device
- * uint8 [batch][height][width], or NULL to keep every velocity); bad[b]
- * (device int32) becomes 1 if sample b has a non-finite value, else 0. */
-lbm_status wsn_nhwc_to_fields(const float *y, const float *shift, const float *scale,
-                              const uint8_t *keep_u, int32_t batch, int32_t height, int32_t width,
-                              float *rho, float *u, int32_t *bad, void *stream);
+/* The inverse direction: f_k = y_k * scale[3 b + k] + shift[3 b + k]
+ * + slope[3 b + k] (x + 1), into the layout of lbm_set_macro; u = 0 wherever
+ * keep_u[b][p] == 0 (keep_u: device uint8 [batch][height][width], or NULL to
+ * keep every velocity); bad[b] (device int32) becomes 1 if sample b has a
+ * non-finite value, else 0. */
+lbm_status wsn_nhwc_to_fields(const float *y, const float *shift, const float *slope,
+                              const float *scale, const uint8_t *keep_u, int32_t batch,
+                              int32_t height, int32_t width, float *rho, float *u, int32_t *bad,
+                              void *stream);
 
 #ifdef __cplusplus
 }

@@ -433,9 +433,13 @@ lbm_status lbm_batch_step(lbm_batch* b, int64_t nsteps) {
 }
 
 lbm_status lbm_batch_run_to_steady(lbm_batch* b, double tol, int64_t max_steps,
-                                   int64_t* steps_out, double* resid_out, int32_t* status_out) {
+                                   int64_t* steps_out, double* resid_out, int32_t* status_out,
+                                   double* q_log, int64_t log_windows) {
   if (!b) return fail(LBM_EINVAL, "batch is NULL");
   if (!(tol >= 0.0) || max_steps < 0) return fail(LBM_EINVAL, "need tol >= 0 and max_steps >= 0");
+  if (log_windows < 0 || (log_windows > 0 && !q_log))
+    return fail(LBM_EINVAL, "q_log must hold log_windows >= 0 rows");
+  for (int64_t i = 0; i < log_windows * b->n; ++i) q_log[i] = NAN;
   const int n = b->n, K = b->K;
   lbm_status s = refresh_args(b);
   if (s != LBM_OK) return s;
@@ -485,12 +489,14 @@ lbm_status lbm_batch_run_to_steady(lbm_batch* b, double tol, int64_t max_steps,
         break;
       }
     }
+    const int64_t window = t / K;   // index of this window in the call
     t += K;
     err = read_q(b, q.data());
     if (err != LBM_OK) break;
     for (int d = 0; d < n; ++d) {
       if (!run[d]) continue;
       done[d] += K;
+      if (window < log_windows) q_log[window * n + d] = q[d];
       if (!isfinite(q[d])) {
         st[d] = LBM_ENONFINITE;
         resid[d] = NAN;

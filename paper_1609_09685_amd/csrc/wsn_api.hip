@@ -580,29 +580,30 @@ lbm_status wsn_pack_input(const uint8_t* solid, const float* feat, int32_t batch
 }
 
 lbm_status wsn_fields_to_nhwc(const float* rho, const float* u, const float* shift,
-                              const float* scale, int32_t batch, int32_t height, int32_t width,
-                              float* y, void* stream) {
+                              const float* slope, const float* scale, int32_t batch,
+                              int32_t height, int32_t width, float* y, void* stream) {
   lbm_status s = check_image(batch, height, width, 3, "wsn_fields_to_nhwc");
   if (s != LBM_OK) return s;
   if (!rho || !u || !shift || !scale || !y) return fail(LBM_EINVAL, "wsn_fields_to_nhwc: NULL buffer");
   const size_t n = (size_t)batch * height * width;
-  k_fields_to_nhwc<<<blocks_for(n), kBlock, 0, (hipStream_t)stream>>>(rho, u, shift, scale,
-                                                                       height * width, n, y);
+  k_fields_to_nhwc<<<blocks_for(n), kBlock, 0, (hipStream_t)stream>>>(rho, u, shift, slope, scale,
+                                                                       height * width, width, n, y);
   HIP_TRY(hipGetLastError());
   return ok();
 }
 
-lbm_status wsn_nhwc_to_fields(const float* y, const float* shift, const float* scale,
-                              const uint8_t* keep_u, int32_t batch, int32_t height, int32_t width,
-                              float* rho, float* u, int32_t* bad, void* stream) {
+lbm_status wsn_nhwc_to_fields(const float* y, const float* shift, const float* slope,
+                              const float* scale, const uint8_t* keep_u, int32_t batch,
+                              int32_t height, int32_t width, float* rho, float* u, int32_t* bad,
+                              void* stream) {
   lbm_status s = check_image(batch, height, width, 3, "wsn_nhwc_to_fields");
   if (s != LBM_OK) return s;
   if (!y || !shift || !scale || !rho || !u || !bad)
     return fail(LBM_EINVAL, "wsn_nhwc_to_fields: NULL buffer");
   const size_t n = (size_t)batch * height * width;
   HIP_TRY(hipMemsetAsync(bad, 0, (size_t)batch * sizeof(int32_t), (hipStream_t)stream));
-  k_nhwc_to_fields<<<blocks_for(n), kBlock, 0, (hipStream_t)stream>>>(y, shift, scale, keep_u,
-                                                                       height * width, n, rho, u, bad);
+  k_nhwc_to_fields<<<blocks_for(n), kBlock, 0, (hipStream_t)stream>>>(
+      y, shift, slope, scale, keep_u, height * width, width, n, rho, u, bad);
   HIP_TRY(hipGetLastError());
   return ok();
 }

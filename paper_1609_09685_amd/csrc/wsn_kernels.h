@@ -508,37 +508,50 @@ __global__ __launch_bounds__(kBlock) void k_pack_input(const uint8_t* __restrict
 }
 
 // Solver fields (rho [b][p], u [b][2][p]) -> NHWC [b][p][3]:
-// y_k = (f_k - shift[3b + k]) * scale[3b + k].
+// y_k = (f_k - shift[3b + k] - slope[3b + k] (x + 1)) * scale[3b + k], with x
+// the pixel's column (slope may be null: 0).  A slope along x lets the
+// network see the density without its linear drop between the ghost planes,
+// which no translation-invariant map could produce.
 __global__ __launch_bounds__(kBlock) void k_fields_to_nhwc(const float* __restrict__ rho,
                                                            const float* __restrict__ u,
                                                            const float* __restrict__ shift,
+                                                           const float* __restrict__ slope,
                                                            const float* __restrict__ scale, int hw,
-                                                           size_t npix, float* __restrict__ y) {
+                                                           int width, size_t npix,
+                                                           float* __restrict__ y) {
   const size_t p = (size_t)blockIdx.x * kBlock + threadIdx.x;
   if (p >= npix) return;
   const size_t b = p / hw, q = p % hw;
+  const float xp = (float)(q % width + 1);
   const float f[3] = {rho[p], u[(2 * b) * hw + q], u[(2 * b + 1) * hw + q]};
-  for (int k = 0; k < 3; ++k) y[3 * p + k] = (f[k] - shift[3 * b + k]) * scale[3 * b + k];
+  for (int k = 0; k < 3; ++k) {
+    const float base = shift[3 * b + k] + (slope ? slope[3 * b + k] * xp : 0.f);
+    y[3 * p + k] = (f[k] - base) * scale[3 * b + k];
+  }
 }
 
-// NHWC [b][p][3] -> solver fields: f_k = y_k * scale[3b + k] + shift[3b + k];
-// the velocity is zero where keep_u[p] == 0 (when keep_u is given).  A
-// non-finite value anywhere in a sample's prediction is reported in bad[b].
+// NHWC [b][p][3] -> solver fields: f_k = y_k * scale[3b + k] + shift[3b + k]
+// + slope[3b + k] (x + 1); the velocity is zero where keep_u[p] == 0 (when
+// keep_u is given).  A non-finite value anywhere in a sample's prediction is
+// reported in bad[b].
 __global__ __launch_bounds__(kBlock) void k_nhwc_to_fields(const float* __restrict__ y,
                                                            const float* __restrict__ shift,
+                                                           const float* __restrict__ slope,
                                                            const float* __restrict__ scale,
                                                            const uint8_t* __restrict__ keep_u,
-                                                           int hw, size_t npix,
+                                                           int hw, int width, size_t npix,
                                                            float* __restrict__ rho,
                                                            float* __restrict__ u,
                                                            int* __restrict__ bad) {
   const size_t p = (size_t)blockIdx.x * kBlock + threadIdx.x;
   if (p >= npix) return;
   const size_t b = p / hw, q = p % hw;
+  const float xp = (float)(q % width + 1);
   float f[3];
   bool finite = true;
   for (int k = 0; k < 3; ++k) {
-    f[k] = y[3 * p + k] * scale[3 * b + k] + shift[3 * b + k];
+    const float base = shift[3 * b + k] + (slope ? slope[3 * b + k] * xp : 0.f);
+    f[k] = y[3 * p + k] * scale[3 * b + k] + base;
     finite = finite && isfinite(f[k]);
   }
   if (keep_u && !keep_u[p]) f[1] = f[2] = 0.f;

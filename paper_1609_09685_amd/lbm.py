@@ -69,7 +69,7 @@ _SIGS = {
                                     _c.c_void_p]),
     "lbm_batch_step": (_c.c_int, [_c.c_void_p, _c.c_int64]),
     "lbm_batch_run_to_steady": (_c.c_int, [_c.c_void_p, _c.c_double, _c.c_int64, _c.c_void_p,
-                                           _c.c_void_p, _c.c_void_p]),
+                                           _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_int64]),
     "lbm_batch_flux": (_c.c_int, [_c.c_void_p, _c.c_void_p]),
     "lbm_batch_permeability": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p]),
     "lbm_batch_set_option": (_c.c_int, [_c.c_void_p, _c.c_int32, _c.c_int64]),
@@ -367,16 +367,23 @@ class Batch:
     def step(self, n=1):
         _check(self._lib.lbm_batch_step(self._h, int(n)))
 
-    def run_to_steady(self, tol=1e-9, max_steps=10**6):
+    def run_to_steady(self, tol=1e-9, max_steps=10**6, log_windows=0):
         """Returns (status, steps, residual) arrays, one entry per sample (status: LBM_OK,
-        LBM_ENOTCONV or LBM_ENONFINITE).  Never raises for a sample that did not converge."""
+        LBM_ENOTCONV or LBM_ENONFINITE), plus, when log_windows > 0, the flux after
+        each of the first log_windows check windows ([windows, n], NaN after a sample
+        retires).  Never raises for a sample that did not converge."""
         steps = np.zeros(self.n, np.int64)
         resid = np.zeros(self.n)
         status = np.zeros(self.n, np.int32)
+        log = np.zeros((max(int(log_windows), 0), self.n))
         st = self._lib.lbm_batch_run_to_steady(self._h, float(tol), int(max_steps),
                                                steps.ctypes.data, resid.ctypes.data,
-                                               status.ctypes.data)
+                                               status.ctypes.data,
+                                               log.ctypes.data if log.size else None,
+                                               int(log.shape[0]))
         _check(st, allow=(LBM_ENOTCONV, LBM_ENONFINITE))
+        if log_windows:
+            return status, steps, resid, log
         return status, steps, resid
 
     def flux(self):

@@ -75,8 +75,11 @@ def main(argv=None):
     summary = {}
     for name in ("zero", "linear", "learned"):
         s = np.array(ev[name]["steps"])
+        a = np.array(ev[name]["steps_to_k_tol"])
         summary[name] = {"steps_median": float(np.median(s)), "steps_p90": float(np.percentile(s, 90)),
                          "steps_total": int(s.sum()), "seconds": ev[name]["seconds"],
+                         "steps_to_k_tol_median": float(np.median(a)),
+                         "steps_to_k_tol_p90": float(np.percentile(a, 90)),
                          "converged": int(sum(1 for v in ev[name]["status"] if v == 0))}
     for name in ("linear", "learned"):
         summary[name]["k_rel_err_max"] = ev[name]["k_rel_err_max"]
@@ -85,6 +88,9 @@ def main(argv=None):
         summary[name]["reruns"] = ev[name]["reruns"]
     z, l = np.array(ev["zero"]["steps"]), np.array(ev["learned"]["steps"])
     summary["learned"]["step_ratio_median"] = float(np.median(l / z))
+    za, la = np.array(ev["zero"]["steps_to_k_tol"]), np.array(ev["learned"]["steps_to_k_tol"])
+    summary["learned"]["k_tol_step_ratio_median"] = float(np.median(la / za))
+    summary["prediction_error"] = ev["prediction_error"]
     rep["summary"] = summary
     log(json.dumps(summary))
     if args.out:

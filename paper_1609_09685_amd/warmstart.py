@@ -12,9 +12,12 @@ Steps, all on the GPU through the library's entry points:
 1. data: batched solver runs (``lbm.Batch``) of random QSGS masks to the
    steady state, fields read back with ``lbm_get_macro`` and normalised by
    Stokes linearity (``wsn_fields_to_nhwc``):
-       rho' = (rho - rho_bar) / drho,   u' = u nu L / (c_s^2 drho) / U_SCALE,
-   where L = Nx + 1 and drho = rho_in - rho_out: in the Stokes regime both are
-   independent of drho, and u' is a local permeability (Darcy's law);
+       rho' = (rho - rho_lin(x)) / drho,   u' = u nu L / (c_s^2 drho) / U_SCALE,
+   where rho_lin is the linear drop between the ghost planes, L = Nx + 1 and
+   drho = rho_in - rho_out: in the Stokes regime both are independent of
+   drho, u' is a local permeability (Darcy's law), and rho' holds only the
+   local departures from the mean pressure gradient, which a convolutional
+   map can see (absolute position it cannot);
 2. training: masked MSE over fluid nodes, Adam (``wsn_*`` kernels);
 3. start: prediction -> fields (``wsn_nhwc_to_fields``, velocity zero in
    closed pockets) -> ``lbm_set_macro`` -> ``lbm_smooth`` (removes the modes
@@ -34,6 +37,7 @@ NX, NY = 256, 128
 RHO_IN, RHO_OUT = 1.0005, 0.9995
 KN_SCALE = 1e-3          # network input: Kn / KN_SCALE
 CS2 = 1.0 / 3.0
+SMOOTH_PASSES = 4        # lbm_smooth passes (period-2 modes) before using a field
 
 
 def sample(seed, nx=NX, ny=NY):
@@ -50,18 +54,22 @@ def features(taus, nx):
 
 
 def target_maps(taus, nx, u_scale, rho_in=RHO_IN, rho_out=RHO_OUT):
-    """Per-sample (shift, scale) [B, 3] for fields -> normalised targets, and for
-    the inverse direction."""
+    """Per-sample (shift, slope, scale, inverse scale) [B, 3] between solver fields
+    and normalised targets: y = (f - shift - slope (x + 1)) * scale.  The density
+    target is the deviation from the linear drop between the ghost planes,
+    rho_in + (rho_out - rho_in)(x + 1)/(nx + 1), in units of drho."""
     taus = np.asarray(taus, float)
     drho = rho_in - rho_out
-    rho_bar = 0.5 * (rho_in + rho_out)
     nu = (taus - 0.5) / 3.0
     uf = nu * (nx + 1) / (CS2 * drho) / u_scale          # u -> u'
     shift = np.zeros((len(taus), 3))
-    shift[:, 0] = rho_bar
+    shift[:, 0] = rho_in
+    slope = np.zeros((len(taus), 3))
+    slope[:, 0] = (rho_out - rho_in) / (nx + 1)
     fwd = np.stack([np.full_like(uf, 1.0 / drho), uf, uf], 1)
     inv = 1.0 / fwd
-    return shift.astype(np.float32), fwd.astype(np.float32), inv.astype(np.float32)
+    f32 = lambda a: a.astype(np.float32)
+    return f32(shift), f32(slope), f32(fwd), f32(inv)
 
 
 def _dev(a):
@@ -82,8 +90,8 @@ class Dataset:
         return len(self.taus)
 
     def targets(self, u_scale):
-        shift, fwd, _ = target_maps(self.taus, self.x.shape[2], u_scale)
-        return wsn.fields_to_nhwc(self.rho, self.u, _dev(shift), _dev(fwd))
+        shift, slope, fwd, _ = target_maps(self.taus, self.x.shape[2], u_scale)
+        return wsn.fields_to_nhwc(self.rho, self.u, _dev(shift), _dev(fwd), slope=_dev(slope))
 
 
 def solve(masks, taus, precision="fp32", tol=1e-9, max_steps=400000, starts=None, graph=True):
@@ -127,6 +135,10 @@ def generate(seeds, chunk=1024, precision="fp32", tol=1e-9, max_steps=400000, lo
                 dropped["non_finite" if status[j] == lbm.LBM_ENONFINITE else "not_converged"] += 1
                 continue
             i = len(kept)
+            # the converged state may still carry modes that alternate every
+            # step (mostly in u_y, invisible to the x flux); the fields are
+            # read after removing them
+            s.smooth(SMOOTH_PASSES)
             s.macro("float32", out=(rho[i], u[i]))
             solid[i] = torch.as_tensor(smp[j][0]).cuda()
             kept.append(part[j])
@@ -149,9 +161,9 @@ def generate(seeds, chunk=1024, precision="fp32", tol=1e-9, max_steps=400000, lo
 
 def u_scale_of(data, sample_count=64):
     """RMS of u nu L / (c_s^2 drho) over the fluid nodes of the first samples."""
-    shift, fwd, _ = target_maps(data.taus[:sample_count], NX, 1.0)
+    shift, slope, fwd, _ = target_maps(data.taus[:sample_count], NX, 1.0)
     y = wsn.fields_to_nhwc(data.rho[:sample_count].contiguous(), data.u[:sample_count].contiguous(),
-                           _dev(shift), _dev(fwd)).cpu().numpy()
+                           _dev(shift), _dev(fwd), slope=_dev(slope)).cpu().numpy()
     fluid = data.solid[:sample_count].cpu().numpy() == 0
     return float(np.sqrt((y[..., 1:][fluid] ** 2).mean()))
 
@@ -214,36 +226,56 @@ def predict(net, masks, taus, u_scale):
     rho = torch.empty((n, NY, NX), dtype=torch.float32, device="cuda")
     u = torch.empty((n, 2, NY, NX), dtype=torch.float32, device="cuda")
     bad = torch.empty(n, dtype=torch.int32, device="cuda")
-    shift, _, inv = target_maps(taus, NX, u_scale)
+    shift, slope, _, inv = target_maps(taus, NX, u_scale)
     for c0 in range(0, n, net.batch):
         m = min(net.batch, n - c0)
         solid = _dev(np.stack(masks[c0:c0 + m]).astype(np.uint8))
         keep = _dev(np.stack([open_fluid(mk) for mk in masks[c0:c0 + m]]))
         x = wsn.pack_input(solid, _dev(features(taus[c0:c0 + m], NX)))
         y = net.infer(x)
-        wsn.nhwc_to_fields(y, _dev(shift[c0:c0 + m]), _dev(inv[c0:c0 + m]), keep_u=keep,
+        wsn.nhwc_to_fields(y, _dev(shift[c0:c0 + m]), _dev(inv[c0:c0 + m]),
+                           slope=_dev(slope[c0:c0 + m]), keep_u=keep,
                            out=(rho[c0:c0 + m], u[c0:c0 + m], bad[c0:c0 + m]))
     return rho, u, bad
 
 
 ONE_STEP_TOL = 1e-6   # relative flux change over one step that marks a period-2 mode
-SMOOTH_PASSES = 4     # lbm_smooth passes after a start from predicted fields
+K_TOL = 1e-4          # permeability accuracy of the "accurate permeability" measure
 
 
-def run_checked(masks, taus, start, precision, tol, max_steps, rerun_failed=True):
+def steps_to_accuracy(q_log, q_final, start_steps, K, rtol=K_TOL):
+    """First step count after which the logged flux stays within rtol of its
+    converged value (the permeability is proportional to the flux)."""
+    out = np.zeros(len(q_final), np.int64)
+    for d in range(len(q_final)):
+        q = q_log[:, d]
+        q = q[np.isfinite(q)]
+        err = np.abs(q - q_final[d]) / abs(q_final[d])
+        bad = np.nonzero(err > rtol)[0]
+        w = 0 if len(bad) == 0 else bad[-1] + 1
+        out[d] = start_steps[d] + (w + 1) * K
+    return out
+
+
+def run_checked(masks, taus, start, precision, tol, max_steps, rerun_failed=True, after=None,
+                K=100):
     """Runs the samples in one batch from `start(batch)` (which sets every
     solver's initial state and may take time of its own) to the flux residual
     tol, then checks one more step: a converged state whose flux changes by
     more than ONE_STEP_TOL in a single step carries a period-2 oscillation
     that the residual, taken every K (even) steps, cannot see; such samples
-    are rerun from the zero-velocity start, their steps added.  Returns a dict
-    with per-sample status, steps, k, the rerun flags and the wall time."""
+    are rerun from the zero-velocity start, their steps added.  Also reports,
+    from the flux after every check window, the steps after which the
+    permeability stays within K_TOL of its converged value.  `after(batch)`
+    runs before the batch is released.  Returns a dict of per-sample results."""
     import torch
     b = lbm.Batch.from_masks(masks, taus, RHO_IN, RHO_OUT, precision=precision)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     start(b)
-    status, steps, _ = b.run_to_steady(tol, max_steps)
+    start_steps = np.array([s.steps for s in b.solvers])
+    status, steps, _, qlog = b.run_to_steady(tol, max_steps, log_windows=max_steps // K + 1)
+    sec_main = time.perf_counter() - t0
     k, _ = b.permeability()
     q0 = b.flux()
     b.step(1)
@@ -251,21 +283,46 @@ def run_checked(masks, taus, start, precision, tol, max_steps, rerun_failed=True
     one = np.abs(q1 - q0) / np.abs(q0)
     flagged = (status == lbm.LBM_OK) & (one > ONE_STEP_TOL)
     rerun = flagged & rerun_failed
+    acc = steps_to_accuracy(qlog, q0, start_steps, K)
     steps = steps + 1
     if rerun.any():
         idx = np.nonzero(rerun)[0]
         for j in idx:
             b.solvers[j].reset("uniform")
         b2 = lbm.Batch([b.solvers[j] for j in idx])
-        st2, steps2, _ = b2.run_to_steady(tol, max_steps)
+        st2, steps2, _, qlog2 = b2.run_to_steady(tol, max_steps, log_windows=max_steps // K + 1)
         k2, _ = b2.permeability()
+        q2 = b2.flux()
+        acc2 = steps_to_accuracy(qlog2, q2, np.zeros(len(idx), np.int64), K)
+        acc[idx] = steps[idx] + acc2
         status[idx], steps[idx], k[idx] = st2, steps[idx] + steps2, k2
         b2.close()
     torch.cuda.synchronize()
     sec = time.perf_counter() - t0
+    if after is not None:
+        after(b)
     b.close()
     return dict(status=status.tolist(), steps=steps.tolist(), k=k.tolist(), seconds=sec,
+                seconds_to_residual=sec_main, steps_to_k_tol=acc.tolist(),
                 one_step_change=one.tolist(), flagged=int(flagged.sum()), reruns=int(rerun.sum()))
+
+
+def field_errors(pred_rho, pred_u, ref_rho, ref_u, solid, taus, u_scale):
+    """RMS error of the prediction over fluid nodes in the network's units
+    (the targets rho', u'), per channel, over all samples, with the RMS of the
+    reference targets."""
+    shift, slope, fwd, _ = target_maps(taus, NX, u_scale)
+    xp = np.arange(1, NX + 1, dtype=np.float64)[None, None, :]
+    fl = solid == 0
+    out = {}
+    for c, (p, r) in enumerate(((pred_rho, ref_rho), (pred_u[:, 0], ref_u[:, 0]),
+                                (pred_u[:, 1], ref_u[:, 1]))):
+        base = shift[:, c][:, None, None] + slope[:, c][:, None, None] * xp
+        e = (p - r) * fwd[:, c][:, None, None]
+        ref = (r - base) * fwd[:, c][:, None, None]
+        out[("rho", "ux", "uy")[c]] = dict(rms_err=float(np.sqrt((e[fl] ** 2).mean())),
+                                           rms_ref=float(np.sqrt((ref[fl] ** 2).mean())))
+    return out
 
 
 def evaluate(net, seeds, u_scale, tol=1e-9, max_steps=600000, precision="fp64", log=None):
@@ -285,9 +342,18 @@ def evaluate(net, seeds, u_scale, tol=1e-9, max_steps=600000, precision="fp64", 
             s.reset("linear")
 
     info = {}
+    ref = {}
+
+    def keep_fields(b):
+        for s in b.solvers:
+            s.smooth(SMOOTH_PASSES)
+        rho = np.stack([s.macro("float32")[0].cpu().numpy()[0] for s in b.solvers])
+        u = np.stack([s.macro("float32")[1].cpu().numpy()[:, 0] for s in b.solvers])
+        ref["rho"], ref["u"] = rho, u
 
     def learned(b):
         rho, u, bad = predict(net, masks, taus, u_scale)
+        info["pred"] = (rho.cpu().numpy(), u.cpu().numpy())
         badh = bad.cpu().numpy()
         for j, s in enumerate(b.solvers):
             if badh[j]:
@@ -300,14 +366,24 @@ def evaluate(net, seeds, u_scale, tol=1e-9, max_steps=600000, precision="fp64", 
     # the zero start is the plain method: judged by the same check, never rerun
     for name, fn in (("zero", zero), ("linear", linear), ("learned", learned)):
         out[name] = run_checked(masks, taus, fn, precision, tol, max_steps,
-                                rerun_failed=name != "zero")
+                                rerun_failed=name != "zero",
+                                after=keep_fields if name == "zero" else None)
     out["learned"]["fallbacks"] = info["fallbacks"]
+    out["prediction_error"] = field_errors(info["pred"][0], info["pred"][1], ref["rho"], ref["u"],
+                                           np.stack(masks), np.asarray(taus), u_scale)
     kz = np.array(out["zero"]["k"])
+    okz = np.array(out["zero"]["status"]) == lbm.LBM_OK
     for name in ("linear", "learned"):
-        out[name]["k_rel_err_max"] = float(np.max(np.abs(np.array(out[name]["k"]) - kz) / np.abs(kz)))
+        both = okz & (np.array(out[name]["status"]) == lbm.LBM_OK)
+        e = np.abs(np.array(out[name]["k"]) - kz) / np.abs(kz)
+        out[name]["k_rel_err_max"] = float(e[both].max()) if both.any() else float("nan")
+        out[name]["k_compared"] = int(both.sum())
     if log:
         for name in ("zero", "linear", "learned"):
             s = np.array(out[name]["steps"])
+            a = np.array(out[name]["steps_to_k_tol"])
             log(f"{name:8s}: steps median {np.median(s):.0f} p90 {np.percentile(s, 90):.0f}, "
-                f"{out[name]['seconds']:.2f} s, reruns {out[name]['reruns']}")
+                f"to k within {K_TOL:g}: median {np.median(a):.0f}, {out[name]['seconds']:.2f} s, "
+                f"reruns {out[name]['reruns']}")
+        log(f"prediction error (network units): {out['prediction_error']}")
     return out

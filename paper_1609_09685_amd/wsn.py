@@ -43,8 +43,8 @@ _SIGS = {
     "wsn_upcat_forward": (_c.c_int, [_p, _p, _p, _i, _i, _i, _i, _i, _p]),
     "wsn_upcat_backward": (_c.c_int, [_p, _p, _p, _i, _i, _i, _i, _i, _p]),
     "wsn_pack_input": (_c.c_int, [_p, _p, _i, _i, _i, _p, _p]),
-    "wsn_fields_to_nhwc": (_c.c_int, [_p, _p, _p, _p, _i, _i, _i, _p, _p]),
-    "wsn_nhwc_to_fields": (_c.c_int, [_p, _p, _p, _p, _i, _i, _i, _p, _p, _p, _p]),
+    "wsn_fields_to_nhwc": (_c.c_int, [_p, _p, _p, _p, _p, _i, _i, _i, _p, _p]),
+    "wsn_nhwc_to_fields": (_c.c_int, [_p, _p, _p, _p, _p, _i, _i, _i, _p, _p, _p, _p]),
 }
 
 _lib = None
@@ -195,19 +195,22 @@ def pack_input(solid, feat, out=None):
     return x
 
 
-def fields_to_nhwc(rho, u, shift, scale):
-    """rho [B,H,W], u [B,2,H,W] -> y [B,H,W,3] = (f - shift) * scale (per sample, channel)."""
+def fields_to_nhwc(rho, u, shift, scale, slope=None):
+    """rho [B,H,W], u [B,2,H,W] -> y [B,H,W,3] = (f - shift - slope (x + 1)) * scale
+    (per sample and channel; slope optional)."""
     import torch
     B, H, W = rho.shape
     y = torch.empty((B, H, W, 3), dtype=torch.float32, device=rho.device)
     _check(lib().wsn_fields_to_nhwc(_ptr(_f32(rho)), _ptr(_f32(u)), _ptr(_f32(shift)),
+                                    _ptr(None if slope is None else _f32(slope)),
                                     _ptr(_f32(scale)), B, H, W, _ptr(y), _stream(rho.device)))
     return y
 
 
-def nhwc_to_fields(y, shift, scale, keep_u=None, out=None):
-    """y [B,H,W,3] -> (rho [B,H,W], u [B,2,H,W], bad [B] int32) with f = y * scale + shift,
-    u = 0 where keep_u (uint8 [B,H,W]) is 0, into the tensors of `out` if given."""
+def nhwc_to_fields(y, shift, scale, slope=None, keep_u=None, out=None):
+    """y [B,H,W,3] -> (rho [B,H,W], u [B,2,H,W], bad [B] int32) with
+    f = y * scale + shift + slope (x + 1), u = 0 where keep_u (uint8 [B,H,W]) is 0,
+    into the tensors of `out` if given."""
     import torch
     B, H, W, _ = y.shape
     if out is not None:
@@ -222,9 +225,10 @@ def nhwc_to_fields(y, shift, scale, keep_u=None, out=None):
     if keep_u is not None and (keep_u.dtype != torch.uint8 or tuple(keep_u.shape) != (B, H, W)
                                or not keep_u.is_contiguous()):
         raise ValueError("keep_u must be a contiguous uint8 [B,H,W] tensor")
-    _check(lib().wsn_nhwc_to_fields(_ptr(_f32(y)), _ptr(_f32(shift)), _ptr(_f32(scale)),
-                                    _ptr(keep_u), B, H, W, _ptr(rho), _ptr(u), _ptr(bad),
-                                    _stream(y.device)))
+    _check(lib().wsn_nhwc_to_fields(_ptr(_f32(y)), _ptr(_f32(shift)),
+                                    _ptr(None if slope is None else _f32(slope)),
+                                    _ptr(_f32(scale)), _ptr(keep_u), B, H, W, _ptr(rho), _ptr(u),
+                                    _ptr(bad), _stream(y.device)))
     return rho, u, bad
 
 

@@ -165,7 +165,7 @@ def test_batch_entry_points_validate():
     assert not h.value
     assert lib.lbm_batch_create(None, 1, nulls, 1 << 20, None) == lbm.LBM_EINVAL
     for call in (lambda: lib.lbm_batch_step(None, 1),
-                 lambda: lib.lbm_batch_run_to_steady(None, 1e-9, 10, None, None, None),
+                 lambda: lib.lbm_batch_run_to_steady(None, 1e-9, 10, None, None, None, None, 0),
                  lambda: lib.lbm_batch_flux(None, None),
                  lambda: lib.lbm_batch_permeability(None, None, None),
                  lambda: lib.lbm_batch_set_option(None, lbm.LBM_BATCH_OPT_GRAPH, 1)):

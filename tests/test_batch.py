@@ -168,3 +168,17 @@ def test_autotune_picks_a_candidate_and_stays_bitwise(tmp_path, monkeypatch):
         s = lbm.Solver(m, 0.8, precision="fp32", **RHO)
         s.step(250)
         assert np.array_equal(_bytes(s), _bytes(b.solvers[j]))
+
+
+def test_batch_flux_log():
+    """The per-window flux log ends at each sample's retirement and its last two
+    entries give the reported residual."""
+    masks = _masks_2d()[:3]
+    b = lbm.Batch.from_masks(masks, [0.8, 0.6, 1.0], RHO["rho_in"], RHO["rho_out"],
+                             precision="fp64")
+    status, steps, resid, log = b.run_to_steady(1e-7, 30000, log_windows=400)
+    for d in range(3):
+        q = log[:, d]
+        n = int(np.isfinite(q).sum())
+        assert n == steps[d] // 100 and np.isfinite(q[:n]).all() and np.isnan(q[n:]).all()
+        assert abs(q[n - 1] - q[n - 2]) / abs(q[n - 1]) == resid[d]

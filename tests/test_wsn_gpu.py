@@ -260,3 +260,37 @@ def test_training_reduces_loss():
     solid = torch.tensor(x[..., 0].astype(np.uint8), device="cuda")
     losses = [n.train_step(xs, ts, solid, 3e-3).item() for _ in range(60)]
     assert losses[-1] < 0.25 * losses[0], losses[::10]
+
+
+def test_field_conversions():
+    """Solver fields <-> network layout: the affine map with an x slope, the
+    velocity mask, the non-finite flag and the input packing."""
+    B, H, W = 3, 16, 32
+    rho = f32(1.0 + 1e-3 * RNG.standard_normal((B, H, W)))
+    u = f32(1e-4 * RNG.standard_normal((B, 2, H, W)))
+    shift = f32(RNG.standard_normal((B, 3)))
+    slope = f32(1e-3 * RNG.standard_normal((B, 3)))
+    scale = f32(RNG.uniform(0.5, 2.0, (B, 3)))
+    xp = np.arange(1, W + 1)[None, None, :]
+    f = [rho, u[:, 0], u[:, 1]]
+    ref = np.stack([(f[k] - shift[:, k, None, None] - slope[:, k, None, None] * xp)
+                    * scale[:, k, None, None] for k in range(3)], -1)
+    y = wsn.fields_to_nhwc(dev(rho), dev(u), dev(shift), dev(scale), slope=dev(slope))
+    assert np.allclose(y.cpu().numpy(), ref, rtol=1e-5, atol=1e-6)
+    keep = (RNG.random((B, H, W)) < 0.7).astype(np.uint8)
+    yy = y.clone()
+    yy[1, 3, 4, 2] = float("nan")
+    r2, u2, bad = wsn.nhwc_to_fields(yy, dev(shift), dev(1.0 / scale), slope=dev(slope),
+                                     keep_u=torch.tensor(keep, device="cuda"))
+    assert bad.cpu().tolist() == [0, 1, 0]
+    assert np.allclose(r2.cpu().numpy(), rho, rtol=0, atol=1e-5)
+    u2 = u2.cpu().numpy()
+    assert (u2[np.broadcast_to(keep[:, None] == 0, u.shape)] == 0).all()
+    ok = np.broadcast_to(keep[:, None] == 1, u.shape).copy()
+    ok[1, 1, 3, 4] = False                       # the planted NaN
+    assert np.allclose(u2[ok], u[ok], rtol=0, atol=1e-6)
+    solid = (RNG.random((B, H, W)) < 0.3).astype(np.uint8)
+    feat = np.array([0.1, 0.5, 1.7], np.float32)
+    x = wsn.pack_input(torch.tensor(solid, device="cuda"), dev(feat)).cpu().numpy()
+    assert np.array_equal(x[..., 0], solid.astype(np.float32))
+    assert np.array_equal(x[..., 1], np.broadcast_to(feat[:, None, None], (B, H, W)))
