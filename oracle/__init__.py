@@ -55,6 +55,8 @@ def _load():
     lib.oracle_collide.argtypes = [_i, _p, _d, _i, _p]
     lib.oracle_knudsen.argtypes = [_d, _i]
     lib.oracle_knudsen.restype = _d
+    lib.oracle_set_periodic.argtypes = [_p, _i, _d, _d]
+    lib.oracle_set_periodic.restype = _i
     lib.oracle_set_threads.argtypes = [_i]
     lib.oracle_threads.restype = _i
     _lib = lib
@@ -123,7 +125,11 @@ class Oracle:
     Q: 9 (D2Q9, mask (ny, nx)) or 19 (D3Q19, mask (nz, ny, nx)).
     """
 
-    def __init__(self, Q, mask, tau, rho_in, rho_out, linear_eq=False, start="uniform"):
+    def __init__(self, Q, mask, tau, rho_in, rho_out, linear_eq=False, start="uniform",
+                 periodic=False, force=0.0, rho0=1.0):
+        """periodic=True: six periodic faces and a body force of density `force`
+        (= rho0 g) along x, the paper's 3D case; rho_in = rho_out is then the
+        starting density."""
         lib = _load()
         m = np.ascontiguousarray(mask, dtype=np.uint8)
         if m.ndim == 2:
@@ -137,6 +143,9 @@ class Oracle:
         if not self._h:
             raise ValueError("oracle_create rejected the arguments")
         self._lib = lib
+        self.periodic, self.force, self.rho0 = bool(periodic), float(force), float(rho0)
+        if lib.oracle_set_periodic(self._h, int(self.periodic), self.force, self.rho0) != 0:
+            raise ValueError("a body force needs the periodic case")
         self.init_rest(start)
 
     def __del__(self):

@@ -20,7 +20,10 @@
  *   - the Darcy permeability from the mass flow rate (Results, first
  *     paragraph), i.e. Eq. 2 with the body force replaced by the pressure
  *     gradient per unit density;
- *   - Kn = sqrt(pi/6) (tau - 1/2) / Nx (discussion of Fig. 2).
+ *   - Kn = sqrt(pi/6) (tau - 1/2) / Nx (discussion of Fig. 2);
+ *   - the paper's 3D case: force-driven flow with six periodic faces and the
+ *     permeability of Eq. 2, with the body force entering by the forcing of
+ *     Guo, Zheng & Shi (2002) (the paper names no scheme).
  * The readings of what the paper leaves unstated (solid boundary rule, the
  * pressure-boundary mechanism, the flux definition, the convergence test) are
  * listed with the design notes of the repository.
@@ -43,6 +46,9 @@ typedef struct {
   int opp[QMAX], my[QMAX], mz[QMAX];
   double tau, rho_in, rho_out;
   int linear_eq;          /* 1: equilibrium without the terms nonlinear in u */
+  int periodic;           /* 1: all six faces periodic (force-driven case) */
+  double force;           /* body-force density along x, F = rho0 g (periodic case) */
+  double rho0;            /* reference density of the force and of Eq. 2 */
   unsigned char *solid;   /* [nz][ny][nx], 1 = solid */
   double *f;              /* post-collision populations of the current step */
   double *tmp;
@@ -134,6 +140,16 @@ static double pulled(const oracle_t *o, int x, int y, int z, int i) {
   const int Q = o->Q;
   int sx = x - o->c[i][0], sy = y - o->c[i][1], sz = z - o->c[i][2];
   int k = i;
+  long long here = node(o, x, y, z);
+  if (o->periodic) {
+    /* the source wraps around every face; solid sources bounce back */
+    sx = (sx + o->nx) % o->nx;
+    sy = (sy + o->ny) % o->ny;
+    sz = (sz + o->nz) % o->nz;
+    long long s = node(o, sx, sy, sz);
+    if (o->solid[s]) return f[here * Q + o->opp[i]];
+    return f[s * Q + i];
+  }
   /* symmetric planes half a spacing outside the first/last row */
   if (sy < 0 || sy >= o->ny) {
     sy = sy < 0 ? 0 : o->ny - 1;
@@ -143,7 +159,6 @@ static double pulled(const oracle_t *o, int x, int y, int z, int i) {
     sz = sz < 0 ? 0 : o->nz - 1;
     k = o->mz[k];
   }
-  long long here = node(o, x, y, z);
   if (sx >= 0 && sx < o->nx) {
     long long s = node(o, sx, sy, sz);
     if (o->solid[s]) return f[here * Q + o->opp[i]]; /* halfway bounce-back */
@@ -160,12 +175,31 @@ static double pulled(const oracle_t *o, int x, int y, int z, int i) {
   return f[b * Q + k] + o->w[i] * (rho_set - rho_b) * poly(o, k, u_b);
 }
 
+/* BGK collision.  With a body force F = (force, 0, 0) the forcing of Guo,
+ * Zheng & Shi (2002): the equilibrium takes u = (j + F/2)/rho and the
+ * population i gains (1 - 1/(2 tau)) F_i with
+ *   F_i = w_i [3 (c_i - u).F + 9 (c_i.u)(c_i.F)],
+ * or F_i = 3 w_i c_i.F with the linear equilibrium (both linear in the
+ * deviations from rest then). */
 static void collide(const oracle_t *o, const double *fin, double *fout) {
   double rho, u[3];
   moments(o, fin, &rho, u);
+  const double F = o->force;
+  if (F != 0.0) u[0] += 0.5 * F / rho;
   for (int i = 0; i < o->Q; ++i) {
     double feq = o->w[i] * rho * poly(o, i, u);
     fout[i] = fin[i] - (fin[i] - feq) / o->tau;
+    if (F != 0.0) {
+      double cx = o->c[i][0];
+      double Fi;
+      if (o->linear_eq) {
+        Fi = 3.0 * o->w[i] * cx * F;
+      } else {
+        double cu = o->c[i][0] * u[0] + o->c[i][1] * u[1] + o->c[i][2] * u[2];
+        Fi = o->w[i] * (3.0 * (cx - u[0]) * F + 9.0 * cu * cx * F);
+      }
+      fout[i] += (1.0 - 0.5 / o->tau) * Fi;
+    }
   }
 }
 
@@ -211,6 +245,17 @@ oracle_t *oracle_create(int Q, int nx, int ny, int nz, const unsigned char *soli
   /* Solid slots are never read: they hold NaN so that any read would show. */
   for (long long n = 0; n < N * Q; ++n) o->f[n] = o->tmp[n] = NAN;
   return o;
+}
+
+/* Periodic, force-driven case (the paper's 3D experiment): all six faces
+ * periodic and a body force along x of density force = rho0 g.  periodic = 0
+ * returns to the pressure-driven case (force must then be 0). */
+int oracle_set_periodic(oracle_t *o, int periodic, double force, double rho0) {
+  if (!periodic && force != 0.0) return -1;
+  o->periodic = periodic ? 1 : 0;
+  o->force = force;
+  o->rho0 = rho0;
+  return 0;
 }
 
 void oracle_destroy(oracle_t *o) {
@@ -279,13 +324,17 @@ void oracle_macro(const oracle_t *o, double *rho, double *u) {
 }
 
 /* Mass flow rate: x-momentum summed over the fluid nodes, divided by nx, i.e.
- * the mean over x of the mass flux through a cross-section. */
+ * the mean over x of the mass flux through a cross-section.  With a body
+ * force the momentum of a node is rho u = j - F/2 in terms of its stored
+ * (post-collision) populations, whose momentum already holds the step's F. */
 double oracle_flux(const oracle_t *o) {
   double s = 0.0;
   long long N = (long long)o->nx * o->ny * o->nz;
   for (long long n = 0; n < N; ++n) {
     if (o->solid[n]) continue;
-    for (int i = 0; i < o->Q; ++i) s += o->c[i][0] * o->f[n * o->Q + i];
+    double j = 0.0;
+    for (int i = 0; i < o->Q; ++i) j += o->c[i][0] * o->f[n * o->Q + i];
+    s += j - 0.5 * o->force;
   }
   return s / o->nx;
 }
@@ -306,6 +355,13 @@ double oracle_mass(const oracle_t *o) {
  * L = nx + 1 (distance between the density-imposing ghost planes), A = ny*nz. */
 double oracle_permeability(const oracle_t *o) {
   double nu = (o->tau - 0.5) / 3.0;
+  if (o->periodic) {
+    /* Eq. 2: kappa = nu <u>_Omega / g, <u>_Omega = sum_fluid u_x / N_grid,
+     * with rho u / rho0 for u (Stokes regime) and g = force / rho0:
+     * kappa = nu (nx Q_m) / (N_grid force) */
+    double N = (double)o->nx * o->ny * o->nz;
+    return nu * oracle_flux(o) * o->nx / (N * o->force);
+  }
   double L = o->nx + 1.0, A = (double)o->ny * o->nz;
   return nu * oracle_flux(o) * L / (A * (1.0 / 3.0) * (o->rho_in - o->rho_out));
 }
