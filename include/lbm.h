@@ -19,6 +19,8 @@
  *                  by non-equilibrium extrapolation from the edge node
  *                  (Guo, Zheng & Shi 2002); a ghost copies the solidity of the
  *                  edge node it extrapolates from.
+ * With LBM_BC_PERIODIC the faces wrap instead, the flow is driven by the body
+ * force, and rho_in = rho_out is the starting density.
  * Lengths are in lattice units; the permeability is in dx^2 with the pressure
  * gradient taken between the ghost planes: k = nu Q L / (A c_s^2 (rho_in -
  * rho_out)), L = nx + 1, A = ny * nz, c_s^2 = 1/3, and Q the mass flow rate,
@@ -72,6 +74,12 @@ typedef enum {
 enum { LBM_D2Q9 = 9, LBM_D3Q19 = 19 };
 enum { LBM_FP64 = 0, LBM_FP32 = 1 };          /* storage and in-kernel arithmetic */
 enum { LBM_START_UNIFORM = 0, LBM_START_LINEAR = 1 };
+/* Boundary cases: pressure-driven flow along x (density on ghost planes at
+ * x = -1 and x = nx, symmetric y / z faces; the paper's 2D case), or the
+ * paper's 3D case: all six faces periodic and a body force along x, with the
+ * permeability of Eq. 2, kappa = nu <u>_Omega / g, <u>_Omega the x-velocity
+ * summed over the fluid nodes per grid node (rho u / rho0 for u). */
+enum { LBM_BC_PRESSURE = 0, LBM_BC_PERIODIC = 1 };
 enum {
   LBM_OPT_XCD_REMAP = 1,  /* tile order over the 8 XCDs when LBM_OPT_BAND is 0: 0 hardware
                              order; 1 one contiguous eighth per XCD (default); m >= 2 chunks
@@ -91,6 +99,10 @@ typedef struct {
   int32_t check_every;  /* K: steps between two convergence checks (>= 1)          */
   double rho0;          /* reference density of the deviation storage (> 0)        */
   int64_t n_fluid;      /* number of fluid (0) voxels in the mask; lbm_init checks it */
+  int32_t boundary;     /* LBM_BC_PRESSURE (0, default) or LBM_BC_PERIODIC             */
+  double body_force;    /* LBM_BC_PERIODIC: acceleration g along x (force density
+                           rho0 g, forcing of Guo, Zheng & Shi 2002); must be 0 with
+                           LBM_BC_PRESSURE                                          */
 } lbm_geom;
 
 typedef struct {
@@ -122,7 +134,10 @@ lbm_status lbm_reset(lbm_ctx *ctx, int32_t start);
 /* Restarts from given macroscopic fields: every fluid node gets the
  * equilibrium populations of (rho, u).  rho: device float32 [nz][ny][nx];
  * u: device float32 [D][nz][ny][nx] (D = 2 for D2Q9, 3 for D3Q19).  Values at
- * solid nodes are ignored.  Resets the step count. */
+ * solid nodes are ignored.  Resets the step count.  With a body force F
+ * (periodic case) u is the velocity of the forcing scheme, as lbm_get_macro
+ * reports it: the stored populations are the equilibrium of rho and
+ * u + F/(2 rho). */
 lbm_status lbm_set_macro(lbm_ctx *ctx, const float *rho, const float *u);
 
 /* Damps the lattice modes that change sign every step (eigenvalue -1 of the
@@ -155,7 +170,10 @@ lbm_status lbm_run_to_steady(lbm_ctx *ctx, double tol, int64_t max_steps,
 
 /* Macroscopic fields of the current state into caller device buffers:
  * rho [nz][ny][nx], u [D][nz][ny][nx]; dtype 0 = float32, 1 = float64.
- * Solid nodes get rho = rho0 and u = 0. */
+ * Solid nodes get rho = rho0 and u = 0.  With a body force F (periodic case)
+ * u = (j - F/2)/rho, j the momentum of the stored post-collision populations:
+ * the velocity of the forcing scheme's collision in the last step, which
+ * Eq. 2 averages. */
 lbm_status lbm_get_macro(lbm_ctx *ctx, void *rho, void *u, int32_t dtype);
 
 /* Checkpoint / restore: copies the current population buffer (f_bytes, the
@@ -203,7 +221,7 @@ const char *lbm_version(void);
  * samples one by one (same tiles, same deterministic reductions).
  *
  * Requirements: 1 <= n samples, all with the same lattice, precision,
- * check_every and linear-equilibrium option, all on the batch's stream (the
+ * check_every, boundary case and linear-equilibrium option, all on the batch's stream (the
  * stream given to lbm_batch_create).  While a batch exists its contexts may
  * still be used directly (on that stream), but their tile-order options must
  * not change.  Convergence: after every window of K = check_every steps the

@@ -310,7 +310,10 @@ void oracle_step(oracle_t *o, long long n) {
 
 long long oracle_steps(const oracle_t *o) { return o->steps; }
 
-/* Density and velocity of every node (NaN on solids). */
+/* Density and velocity of every node (NaN on solids).  With a body force the
+ * stored populations are post-collision and hold the whole step's force, so
+ * the velocity of the forcing scheme is u = (j - F/2)/rho, the same velocity
+ * the flux and Eq. 2 use. */
 void oracle_macro(const oracle_t *o, double *rho, double *u) {
   long long N = (long long)o->nx * o->ny * o->nz;
   for (long long n = 0; n < N; ++n) {
@@ -320,6 +323,7 @@ void oracle_macro(const oracle_t *o, double *rho, double *u) {
       continue;
     }
     moments(o, o->f + n * o->Q, rho + n, u + 3 * n);
+    if (o->force != 0.0) u[3 * n] -= 0.5 * o->force / rho[n];
   }
 }
 

@@ -104,6 +104,13 @@ inline FastDiv make_fastdiv(uint32_t d) {
   return f;
 }
 
+// Body-force density F = rho0 g along x in the storage precision T, as the
+// kernels apply it (0 in the pressure-driven case).
+template <class T>
+inline T force_density(const lbm_ctx* c) {
+  return c->g.boundary == LBM_BC_PERIODIC ? (T)(c->g.rho0 * c->g.body_force) : T(0);
+}
+
 template <class T>
 StepArgs<T> step_args(const lbm_ctx* c) {
   StepArgs<T> a;
@@ -139,6 +146,7 @@ StepArgs<T> step_args(const lbm_ctx* c) {
   a.nbands = a.band > 0 ? (a.tiles_y + a.band - 1) / a.band : 0;
   a.dv_band_blocks = make_fastdiv((uint32_t)(a.band > 0 ? c->g.nz * a.band * a.tiles_x : 1));
   a.dv_band_plane = make_fastdiv((uint32_t)(a.band > 0 ? a.band * a.tiles_x : 1));
+  a.fx = force_density<T>(c);
   a.omega = (T)(1.0 / c->tau);
   a.rho0 = (T)c->g.rho0;
   a.drho_in = (T)(c->rho_in - c->g.rho0);
@@ -158,6 +166,16 @@ int step_grid(const lbm_ctx* c, const StepArgs<T>& a) {
   if (a.band > 0) return (int)(align_up((size_t)a.nbands, 8) * a.dv_band_blocks.d);
   if (c->xcd_remap == 0) return a.blocks;
   return (int)align_up((size_t)a.blocks, (size_t)(c->xcd_remap == 1 ? 8 : 8 * a.chunk));
+}
+
+// The flux pass sums the x-momentum of the stored populations, which holds
+// the whole step's force; the momentum of a node is rho u = j - F/2, so the
+// pass result is lowered by n_fluid F / (2 nx), with F the force density the
+// kernels use (rounded to the storage precision).
+inline double flux_pass_offset(const lbm_ctx* c) {
+  const double F = c->g.precision == LBM_FP64 ? (double)force_density<double>(c)
+                                              : (double)force_density<float>(c);
+  return (double)c->L.n_fluid * F / (2.0 * c->g.nx);
 }
 
 // Launches the flux pass over the current populations of c; *nparts partials.

@@ -44,6 +44,10 @@
 //      (kept in a double-buffered boundary-plane array); a ghost copies the
 //      solidity of b;
 //   4. otherwise plain streaming, g*_i(x - c_i).
+// Periodic case (the paper's 3D experiment): every face wraps, so the rows
+// and the x-edge lanes pull across the opposite face, with bounce-back at
+// solid sources and no mirrors or ghosts; a body force F = rho0 g along x
+// enters by the forcing of Guo, Zheng & Shi (2002).
 // Collision in deviation form: drho = sum g, j = sum c g, rho = rho0 + drho,
 // u = j / rho, g_eq_i = w_i [drho + rho (3 c_i.u + 9/2 (c_i.u)^2 - 3/2 u.u)],
 // g* = g - (g - g_eq)/tau.  The linear ("Stokes") equilibrium drops the two
@@ -132,6 +136,7 @@ struct StepArgs {
   FastDiv dv_tiles_x, dv_tiles_y, dv_chunk;
   FastDiv dv_band_blocks, dv_band_plane;   // nz * band * tiles_x, band * tiles_x
   T omega, rho0, drho_in, drho_out;  // 1/tau; rho0; rho_in - rho0; rho_out - rho0
+  T fx;                            // body-force density along x (rho0 g), periodic case
 };
 
 // ---------------------------------------------------------------- reductions
@@ -334,6 +339,9 @@ __device__ __forceinline__ uint32_t lane_rank(uint64_t m, uint32_t pfx) {
 struct RowWords {
   uint64_t lo, mid, hi;
   uint32_t base, end_lo, base_hi;
+  // periodic case, x-edge words only: fluid flag (0 / ~0u) and slot of the
+  // row's node nx - 1 (the source x - 1 of x = 0) and of its node 0
+  uint32_t last_fluid, last_slot, first_fluid, first_slot;
 };
 
 // Updates the node x = 64 w + lane of row (y, z); y, z, w are uniform across
@@ -343,13 +351,17 @@ struct RowWords {
 // than 4 GiB, so loads and stores use a uniform group base plus a 32-bit lane
 // offset.  The post-collision populations go to out[i][lds_base + slot] (LDS;
 // lds_base = the block-local position of the segment minus its first slot).
-// Returns the node's x-momentum (0 if the node is not fluid).
-template <class L, class T, bool LINEAR, bool OFF32, bool YZE, bool XE>
+// Returns the node's x-momentum rho u_x (with a body force, j_x + F/2; 0 if
+// the node is not fluid).
+template <class L, class T, bool LINEAR, bool OFF32, bool PER, bool YZE, bool XE>
 __device__ __forceinline__ T node_update(const StepArgs<T>& a, int y, int z, int w, int lane,
                                          T (*out)[kThreads], uint32_t lds_base) {
   const int x = (w << 6) + lane;
-  const bool y0 = YZE && y == 0, y1 = YZE && y == a.ny - 1;
-  const bool z0 = YZE && L::D == 3 && z == 0, z1 = YZE && L::D == 3 && z == a.nz - 1;
+  constexpr bool per = PER;   // faces wrap instead of mirror / ghost (periodic case)
+  // symmetric planes (pressure case only)
+  const bool y0 = YZE && !per && y == 0, y1 = YZE && !per && y == a.ny - 1;
+  const bool z0 = YZE && !per && L::D == 3 && z == 0;
+  const bool z1 = YZE && !per && L::D == 3 && z == a.nz - 1;
   const uint32_t row_self = (uint32_t)z * (uint32_t)a.ny + (uint32_t)y;
   const uint32_t wi_self = row_self * (uint32_t)(a.nw + 2) + 1u + (uint32_t)w;
   const uint32_t pi_self = row_self * (uint32_t)a.nw + (uint32_t)w;
@@ -363,8 +375,15 @@ __device__ __forceinline__ T node_update(const StepArgs<T>& a, int y, int z, int
         constexpr int dy = decltype(iyc)::value - 1;
         int ey = dy, ez = dz;
         if constexpr (YZE) {
-          if ((dy < 0 && y0) || (dy > 0 && y1)) ey = 0;
-          if ((dz < 0 && z0) || (dz > 0 && z1)) ez = 0;
+          if constexpr (PER) {   // wrap to the opposite face
+            if (dy < 0 && y == 0) ey = a.ny - 1;
+            if (dy > 0 && y == a.ny - 1) ey = 1 - a.ny;
+            if (dz < 0 && z == 0) ez = a.nz - 1;
+            if (dz > 0 && z == a.nz - 1) ez = 1 - a.nz;
+          } else {
+            if ((dy < 0 && y0) || (dy > 0 && y1)) ey = 0;
+            if ((dz < 0 && z0) || (dz > 0 && z1)) ez = 0;
+          }
         }
         const int drow = ez * a.ny + ey;
         const uint64_t* wp = a.bits + (wi_self + (uint32_t)(drow * (a.nw + 2)));
@@ -377,6 +396,18 @@ __device__ __forceinline__ T node_update(const StepArgs<T>& a, int y, int z, int
         // neighbour words' slots; at a row end the value is unused (ghost lanes)
         r.end_lo = (w > 0 ? pp[-1] : pp[0]) + (uint32_t)__popcll(r.lo);
         r.base_hi = w + 1 < a.nw ? pp[1] : pp[0];
+        if constexpr (XE && PER) {
+          {   // the nodes across the periodic x faces of this row
+            const uint64_t* row_w = wp - w;
+            const uint32_t* row_p = pp - w;
+            const int bl = (a.nx - 1) & 63;
+            const uint64_t wl = row_w[a.nw - 1];
+            r.last_fluid = (uint32_t)-(int)((wl >> bl) & 1ull);
+            r.last_slot = row_p[a.nw - 1] + (uint32_t)__popcll(wl & ((1ull << bl) - 1ull));
+            r.first_fluid = (uint32_t)-(int)(row_w[0] & 1ull);
+            r.first_slot = row_p[0];
+          }
+        }
       });
     }
   });
@@ -408,14 +439,20 @@ __device__ __forceinline__ T node_update(const StepArgs<T>& a, int y, int z, int
         sf = lane_mask((r.mid << 1) | (r.lo >> 63), lane);
         si = (lane == 0 ? r.end_lo : r0) + sf;
         if constexpr (XE) {
-          if (x0) { sf = lane_mask(r.mid, lane); si = r0; ghm[q] = sf; }
+          if (x0) {
+            if constexpr (PER) { sf = r.last_fluid; si = r.last_slot; }
+            else { sf = lane_mask(r.mid, lane); si = r0; ghm[q] = sf; }
+          }
         }
       } else {                          // source x + 1: slot r0 + fluid(x)
         const uint32_t f0 = lane_mask(r.mid, lane);
         sf = lane_mask((r.mid >> 1) | (r.hi << 63), lane);
         si = lane == 63 ? r.base_hi : r0 - f0;
         if constexpr (XE) {
-          if (x1) { sf = f0; si = r0; ghm[q] = sf; }
+          if (x1) {
+            if constexpr (PER) { sf = r.first_fluid; si = r.first_slot; }
+            else { sf = f0; si = r0; ghm[q] = sf; }
+          }
         }
       }
     }
@@ -445,7 +482,7 @@ __device__ __forceinline__ T node_update(const StepArgs<T>& a, int y, int z, int
   });
 
   // Ghost populations: add the non-equilibrium extrapolation term.
-  if constexpr (XE) {
+  if constexpr (XE && !PER) {
     if (x0 || x1) {
       unroll<1, L::Q>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
@@ -479,18 +516,55 @@ __device__ __forceinline__ T node_update(const StepArgs<T>& a, int y, int z, int
     if constexpr (L::cz[q] == 1) jz += g[q];
     if constexpr (L::cz[q] == -1) jz -= g[q];
   });
-  const T rho = a.rho0 + drho;
-  const T inv = recip(rho);
-  const T ux = jx * inv, uy = jy * inv, uz = jz * inv;
+  // with a body force (Guo et al. 2002) the velocity carries half the step's
+  // force density: rho u = j + F/2
+  T jxe = jx;
+  if constexpr (PER) jxe += T(0.5) * a.fx;
+  // The linear equilibrium w_i (rho + 3 c_i.(rho u)) needs only the momentum:
+  // it is formed from rho u directly (geq with rho = 1, u = rho u), so the
+  // update stays exactly linear in the deviations and the force.
+  T rho, ux, uy, uz;
+  if constexpr (LINEAR) {
+    rho = T(1);
+    ux = jxe;
+    uy = jy;
+    uz = jz;
+  } else {
+    rho = a.rho0 + drho;
+    const T inv = recip(rho);
+    ux = jxe * inv;
+    uy = jy * inv;
+    uz = jz * inv;
+  }
   const T usq15 = T(1.5) * (ux * ux + uy * uy + uz * uz);
-  unroll<0, L::Q>([&](auto qc) {
-    constexpr int q = decltype(qc)::value;
-    const T ge = geq<L, q, LINEAR>(drho, rho, ux, uy, uz, usq15);
-    g[q] = g[q] - a.omega * (g[q] - ge);
-    out[q][lds_base + self] = g[q];
-  });
+  if constexpr (!PER) {
+    unroll<0, L::Q>([&](auto qc) {
+      constexpr int q = decltype(qc)::value;
+      const T ge = geq<L, q, LINEAR>(drho, rho, ux, uy, uz, usq15);
+      g[q] = g[q] - a.omega * (g[q] - ge);
+      out[q][lds_base + self] = g[q];
+    });
+  } else {
+    // forcing term (1 - omega/2) F_i, F_i = w_i [3 (c_i - u).F + 9 (c_i.u)(c_i.F)],
+    // or 3 w_i c_i.F with the linear equilibrium; F = (fx, 0, 0)
+    const T af = (T(1) - T(0.5) * a.omega) * a.fx;
+    unroll<0, L::Q>([&](auto qc) {
+      constexpr int q = decltype(qc)::value;
+      constexpr int cx = L::cx[q];
+      const T ge = geq<L, q, LINEAR>(drho, rho, ux, uy, uz, usq15);
+      T fi;
+      if constexpr (LINEAR) {
+        fi = T(3 * cx) * T(L::w[q]) * af;
+      } else {
+        const T cu = dot_c<L, q>(ux, uy, uz);
+        fi = T(L::w[q]) * af * (T(3) * (T(cx) - ux) + T(9 * cx) * cu);
+      }
+      g[q] = g[q] - a.omega * (g[q] - ge) + fi;
+      out[q][lds_base + self] = g[q];
+    });
+  }
 
-  if constexpr (XE) {
+  if constexpr (XE && !PER) {
     if (x0 || x1) {
       // edge-node moments of the stored state, read by the next step's ghosts
       T bd, bx, by, bz;
@@ -503,21 +577,21 @@ __device__ __forceinline__ T node_update(const StepArgs<T>& a, int y, int z, int
       if constexpr (L::D == 3) bp[3 * plane] = bz;
     }
   }
-  return jx;
+  return jxe;
 }
 
 // Picks the specialisation of node_update for a wave's (y, z, w).
-template <class L, class T, bool LINEAR, bool OFF32>
+template <class L, class T, bool LINEAR, bool OFF32, bool PER>
 __device__ __forceinline__ T wave_update(const StepArgs<T>& a, int y, int z, int w, int lane,
                                          T (*out)[kThreads], uint32_t lds_base) {
   const bool yze = y == 0 || y == a.ny - 1 || (L::D == 3 && (z == 0 || z == a.nz - 1));
   const bool xe = w == 0 || w == ((a.nx - 1) >> 6);
   if (yze) {
-    if (xe) return node_update<L, T, LINEAR, OFF32, true, true>(a, y, z, w, lane, out, lds_base);
-    return node_update<L, T, LINEAR, OFF32, true, false>(a, y, z, w, lane, out, lds_base);
+    if (xe) return node_update<L, T, LINEAR, OFF32, PER, true, true>(a, y, z, w, lane, out, lds_base);
+    return node_update<L, T, LINEAR, OFF32, PER, true, false>(a, y, z, w, lane, out, lds_base);
   }
-  if (xe) return node_update<L, T, LINEAR, OFF32, false, true>(a, y, z, w, lane, out, lds_base);
-  return node_update<L, T, LINEAR, OFF32, false, false>(a, y, z, w, lane, out, lds_base);
+  if (xe) return node_update<L, T, LINEAR, OFF32, PER, false, true>(a, y, z, w, lane, out, lds_base);
+  return node_update<L, T, LINEAR, OFF32, PER, false, false>(a, y, z, w, lane, out, lds_base);
 }
 
 // Order in which tiles meet the hardware.  The dispatcher deals block ids
@@ -555,7 +629,7 @@ __device__ __forceinline__ int logical_block(int hw, const StepArgs<T>& a) {
 // zero).  FLUX: each wave also stores the FP64 sum of its 64 nodes'
 // x-momentum at the index of its bitmap word, (z ny + y) nw + w, so the flux
 // does not depend on the tiling.
-template <class L, class T, bool FLUX, bool LINEAR, bool OFF32>
+template <class L, class T, bool FLUX, bool LINEAR, bool OFF32, bool PER>
 __device__ __forceinline__ void step_tile(const StepArgs<T>& a, const uint32_t hw) {
   __shared__ T out[L::Q][kThreads];
   __shared__ uint32_t seg_first[kRows], seg_count[kRows];
@@ -606,7 +680,7 @@ __device__ __forceinline__ void step_tile(const StepArgs<T>& a, const uint32_t h
   T jx = T(0);
   if (row_ok && w < a.nw) {
     const uint32_t lds_base = (uint32_t)(j * S * kWave) - first;
-    jx = wave_update<L, T, LINEAR, OFF32>(a, y, z, w, lane, out, lds_base);
+    jx = wave_update<L, T, LINEAR, OFF32, PER>(a, y, z, w, lane, out, lds_base);
   }
   if constexpr (FLUX) {
     if (row_ok && w < a.nw) {
@@ -640,9 +714,9 @@ __device__ __forceinline__ void step_tile(const StepArgs<T>& a, const uint32_t h
   }
 }
 
-template <class L, class T, bool FLUX, bool LINEAR, bool OFF32>
+template <class L, class T, bool FLUX, bool LINEAR, bool OFF32, bool PER>
 __global__ __launch_bounds__(kThreads) void k_step(const StepArgs<T> a) {
-  step_tile<L, T, FLUX, LINEAR, OFF32>(a, blockIdx.x);
+  step_tile<L, T, FLUX, LINEAR, OFF32, PER>(a, blockIdx.x);
 }
 
 // One time step of many domains in one launch.  Block b runs block owner[b].y
@@ -652,13 +726,13 @@ __global__ __launch_bounds__(kThreads) void k_step(const StepArgs<T> a) {
 // owner[b].y of the domain's own launch would: the tile orders carry over.
 // args[2 d + flip] holds the arguments of domain d for this step (the two
 // entries of a domain differ by the ping-pong parity).
-template <class L, class T, bool FLUX, bool LINEAR, bool OFF32>
+template <class L, class T, bool FLUX, bool LINEAR, bool OFF32, bool PER>
 __global__ __launch_bounds__(kThreads) void k_step_batch(const StepArgs<T>* __restrict__ args,
                                                          const int2* __restrict__ owner, int flip) {
   const int2 o = owner[blockIdx.x];
   if (o.x < 0) return;   // whole block
   const StepArgs<T> a = args[2 * o.x + flip];
-  step_tile<L, T, FLUX, LINEAR, OFF32>(a, (uint32_t)o.y);
+  step_tile<L, T, FLUX, LINEAR, OFF32, PER>(a, (uint32_t)o.y);
 }
 
 // ------------------------------------------------------------ set-up kernels
@@ -813,7 +887,7 @@ template <class L, class T>
 __global__ __launch_bounds__(256) void k_init_fields(T* __restrict__ f, FluidMap fm,
                                                      const float* __restrict__ rho_f,
                                                      const float* __restrict__ u_f, uint64_t ps,
-                                                     double rho0) {
+                                                     double rho0, double fhalf) {
   const uint64_t N = (uint64_t)fm.nx * fm.ny * fm.nz;
   const uint64_t m = (uint64_t)blockIdx.x * 256 + threadIdx.x;
   if (m >= N) return;
@@ -822,7 +896,8 @@ __global__ __launch_bounds__(256) void k_init_fields(T* __restrict__ f, FluidMap
   bool fluid;
   const uint32_t k = fm.rank(x, (int)(r % fm.ny), (int)(r / fm.ny), fluid);
   if (!fluid) return;
-  const double rho = rho_f[m], ux = u_f[m], uy = u_f[N + m];
+  // stored (post-collision) momentum rho u + F/2 for a body force F along x
+  const double rho = rho_f[m], ux = u_f[m] + fhalf / rho, uy = u_f[N + m];
   const double uz = L::D == 3 ? (double)u_f[2 * N + m] : 0.0;
   const double usq15 = 1.5 * (ux * ux + uy * uy + uz * uz);
   const double drho = rho - rho0;
@@ -855,10 +930,12 @@ __global__ __launch_bounds__(256) void k_bplane(const T* __restrict__ f, FluidMa
 }
 
 // Macroscopic fields (dense): rho and u [D][nz][ny][nx]; solids rho0 and 0.
+// fhalf = F/2 of a body force along x (0 without one): the stored populations
+// are post-collision, so the velocity of the forcing scheme is (j - F/2)/rho.
 template <class L, class T, class O>
 __global__ __launch_bounds__(256) void k_macro(const T* __restrict__ f, FluidMap fm,
                                                O* __restrict__ rho, O* __restrict__ u, uint64_t ps,
-                                               T rho0) {
+                                               T rho0, T fhalf) {
   const uint64_t N = (uint64_t)fm.nx * fm.ny * fm.nz;
   const uint64_t m = (uint64_t)blockIdx.x * 256 + threadIdx.x;
   if (m >= N) return;
@@ -870,6 +947,7 @@ __global__ __launch_bounds__(256) void k_macro(const T* __restrict__ f, FluidMap
   if (fluid)
     stored_moments<L, T>([&](auto qc) { return f[(uint64_t)decltype(qc)::value * ps + k]; }, rho0,
                          d, ux, uy, uz);
+  if (fluid && fhalf != T(0)) ux -= fhalf * recip(rho0 + d);
   rho[m] = (O)((double)rho0 + (double)d);
   u[m] = (O)ux;
   u[N + m] = (O)uy;

@@ -60,6 +60,11 @@ lbm_status validate_geom(const lbm_geom* g) {
   if (g->lattice == LBM_D2Q9 && g->nz != 1) return fail(LBM_EINVAL, "D2Q9 needs nz == 1");
   if (g->check_every < 1) return fail(LBM_EINVAL, "check_every must be >= 1");
   if (!(g->rho0 > 0.0) || !isfinite(g->rho0)) return fail(LBM_EINVAL, "rho0 must be > 0");
+  if (g->boundary != LBM_BC_PRESSURE && g->boundary != LBM_BC_PERIODIC)
+    return fail(LBM_EINVAL, "boundary must be LBM_BC_PRESSURE or LBM_BC_PERIODIC");
+  if (!isfinite(g->body_force)) return fail(LBM_EINVAL, "body_force must be finite");
+  if (g->boundary == LBM_BC_PRESSURE && g->body_force != 0.0)
+    return fail(LBM_EINVAL, "a body force needs LBM_BC_PERIODIC");
   const uint64_t N = (uint64_t)g->nx * g->ny * g->nz;
   if (g->n_fluid < 0 || (uint64_t)g->n_fluid > N)
     return fail(LBM_EINVAL, "n_fluid must be in [0, nx*ny*nz], got %lld", (long long)g->n_fluid);
@@ -124,6 +129,14 @@ lbm_status make_layout(const lbm_geom* g, Layout* L) {
   return LBM_OK;
 }
 
+// The pressure and periodic cases are separate instantiations, so the
+// pressure kernel carries none of the periodic code (registers, occupancy).
+template <class Lat, class T, bool FLUX, bool LIN, bool O32>
+void launch_k_step(const StepArgs<T>& a, int grid, dim3 block, hipStream_t st, bool per) {
+  if (per) k_step<Lat, T, FLUX, LIN, O32, true><<<grid, block, 0, st>>>(a);
+  else k_step<Lat, T, FLUX, LIN, O32, false><<<grid, block, 0, st>>>(a);
+}
+
 template <class Lat, class T>
 lbm_status launch_steps(lbm_ctx* c, int64_t n, bool flux_last) {
   const dim3 block(kWave, kRows);
@@ -132,15 +145,16 @@ lbm_status launch_steps(lbm_ctx* c, int64_t n, bool flux_last) {
     const int grid = step_grid(c, a);
     const bool flux = flux_last && s == n - 1;
     const int variant = (flux ? 1 : 0) | (c->linear_eq ? 2 : 0) | (off32_ok(c) ? 4 : 0);
+    const bool per = c->g.boundary == LBM_BC_PERIODIC;
     switch (variant) {
-      case 0: k_step<Lat, T, false, false, false><<<grid, block, 0, c->stream>>>(a); break;
-      case 1: k_step<Lat, T, true, false, false><<<grid, block, 0, c->stream>>>(a); break;
-      case 2: k_step<Lat, T, false, true, false><<<grid, block, 0, c->stream>>>(a); break;
-      case 3: k_step<Lat, T, true, true, false><<<grid, block, 0, c->stream>>>(a); break;
-      case 4: k_step<Lat, T, false, false, true><<<grid, block, 0, c->stream>>>(a); break;
-      case 5: k_step<Lat, T, true, false, true><<<grid, block, 0, c->stream>>>(a); break;
-      case 6: k_step<Lat, T, false, true, true><<<grid, block, 0, c->stream>>>(a); break;
-      default: k_step<Lat, T, true, true, true><<<grid, block, 0, c->stream>>>(a); break;
+      case 0: launch_k_step<Lat, T, false, false, false>(a, grid, block, c->stream, per); break;
+      case 1: launch_k_step<Lat, T, true, false, false>(a, grid, block, c->stream, per); break;
+      case 2: launch_k_step<Lat, T, false, true, false>(a, grid, block, c->stream, per); break;
+      case 3: launch_k_step<Lat, T, true, true, false>(a, grid, block, c->stream, per); break;
+      case 4: launch_k_step<Lat, T, false, false, true>(a, grid, block, c->stream, per); break;
+      case 5: launch_k_step<Lat, T, true, false, true>(a, grid, block, c->stream, per); break;
+      case 6: launch_k_step<Lat, T, false, true, true>(a, grid, block, c->stream, per); break;
+      default: launch_k_step<Lat, T, true, true, true>(a, grid, block, c->stream, per); break;
     }
     c->parity ^= 1;
     c->steps += 1;
@@ -170,7 +184,8 @@ lbm_status launch_reset(lbm_ctx* c, int mode) {
 template <class Lat, class T>
 lbm_status launch_fields(lbm_ctx* c, const float* rho, const float* u) {
   k_init_fields<Lat, T><<<grid_1d(n_nodes(c)), 256, 0, c->stream>>>(
-      (T*)c->f[c->parity], c->fmap(), rho, u, c->L.ps, c->g.rho0);
+      (T*)c->f[c->parity], c->fmap(), rho, u, c->L.ps, c->g.rho0,
+      0.5 * (double)force_density<T>(c));
   HIP_TRY(hipGetLastError());
   return launch_bplane<Lat, T>(c);
 }
@@ -188,14 +203,15 @@ lbm_status launch_flux(lbm_ctx* c, int* nparts) {
 template <class Lat, class T>
 lbm_status launch_macro(lbm_ctx* c, void* rho, void* u, int dtype) {
   const unsigned nb = grid_1d(n_nodes(c));
+  const T fhalf = T(0.5) * force_density<T>(c);
   if (dtype == 0)
     k_macro<Lat, T, float><<<nb, 256, 0, c->stream>>>((const T*)c->f[c->parity], c->fmap(),
                                                        (float*)rho, (float*)u, c->L.ps,
-                                                       (T)c->g.rho0);
+                                                       (T)c->g.rho0, fhalf);
   else
     k_macro<Lat, T, double><<<nb, 256, 0, c->stream>>>((const T*)c->f[c->parity], c->fmap(),
                                                         (double*)rho, (double*)u, c->L.ps,
-                                                        (T)c->g.rho0);
+                                                        (T)c->g.rho0, fhalf);
   HIP_TRY(hipGetLastError());
   return LBM_OK;
 }
@@ -320,11 +336,15 @@ lbm_status current_flux(lbm_ctx* c, double* q) {
   int n = 0;
   lbm_status s = flux_pass(c, &n);
   if (s != LBM_OK) return s;
-  return reduce_flux(c, n, q);
+  s = reduce_flux(c, n, q);
+  if (s == LBM_OK) *q -= flux_pass_offset(c);
+  return s;
 }
 
 double perm_from_flux(const lbm_ctx* c, double q) {
   const double nu = (c->tau - 0.5) / 3.0;
+  if (c->g.boundary == LBM_BC_PERIODIC)   // Eq. 2: nu <u> / g, <u> = nx q / (rho0 N)
+    return nu * q / (c->g.rho0 * c->g.body_force * (double)c->g.ny * c->g.nz);
   const double L = c->g.nx + 1.0, A = (double)c->g.ny * c->g.nz;
   return nu * q * L / (A * (1.0 / 3.0) * (c->rho_in - c->rho_out));
 }
@@ -358,6 +378,8 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_geom* geom, const lbm_buffers* bufs
     return fail(LBM_EINVAL, "tau must be > 1/2 (positive viscosity), got %g", tau);
   if (!(rho_in > 0.0) || !(rho_out > 0.0) || !isfinite(rho_in) || !isfinite(rho_out))
     return fail(LBM_EINVAL, "rho_in and rho_out must be positive and finite");
+  if (geom->boundary == LBM_BC_PERIODIC && rho_in != rho_out)
+    return fail(LBM_EINVAL, "periodic case: rho_in must equal rho_out (the starting density)");
   if (((uintptr_t)bufs->f[0] | (uintptr_t)bufs->f[1] | (uintptr_t)bufs->work) & 255)
     return fail(LBM_EINVAL, "f[0], f[1] and work must be 256-byte aligned");
   lbm_ctx* c = new (std::nothrow) lbm_ctx();
@@ -395,6 +417,8 @@ lbm_status lbm_reset(lbm_ctx* c, int32_t start) {
   if (!c) return fail(LBM_EINVAL, "ctx is NULL");
   if (start != LBM_START_UNIFORM && start != LBM_START_LINEAR)
     return fail(LBM_EINVAL, "start must be LBM_START_UNIFORM or LBM_START_LINEAR");
+  if (start == LBM_START_LINEAR && c->g.boundary == LBM_BC_PERIODIC)
+    return fail(LBM_EINVAL, "the linear-density start needs the pressure case");
   c->parity = 0;
   c->steps = 0;
   lbm_status s = dispatch<Reset>(c, (int)start);
@@ -429,7 +453,10 @@ lbm_status lbm_flux(lbm_ctx* c, double* q_out) {
 
 lbm_status lbm_permeability(lbm_ctx* c, double* k_out) {
   if (!c || !k_out) return fail(LBM_EINVAL, "NULL argument");
-  if (c->rho_in == c->rho_out) return fail(LBM_ESTATE, "rho_in == rho_out: no pressure drop");
+  if (c->g.boundary == LBM_BC_PRESSURE && c->rho_in == c->rho_out)
+    return fail(LBM_ESTATE, "rho_in == rho_out: no pressure drop");
+  if (c->g.boundary == LBM_BC_PERIODIC && c->g.body_force == 0.0)
+    return fail(LBM_ESTATE, "periodic case without a body force: no driving");
   double q;
   lbm_status s = current_flux(c, &q);
   if (s != LBM_OK) return s;

@@ -34,7 +34,7 @@ struct lbm_batch {
   int n;
   std::vector<lbm_ctx*> ctx;
   int lattice, precision, linear_eq, K;
-  bool off32;
+  bool off32, periodic;
   hipStream_t stream;
   size_t arg_size;
   // device tables
@@ -96,6 +96,8 @@ lbm_status validate_ctxs(int32_t n, lbm_ctx* const* ctxs) {
       return fail(LBM_EINVAL, "sample %d: check_every must match sample 0", d);
     if (c->linear_eq != c0->linear_eq)
       return fail(LBM_EINVAL, "sample %d: the linear-equilibrium option must match sample 0", d);
+    if (c->g.boundary != c0->g.boundary)
+      return fail(LBM_EINVAL, "sample %d: boundary case must match sample 0", d);
     if (off32_ok(c) != off32_ok(c0))
       return fail(LBM_EINVAL, "sample %d: sizes too different to share one step kernel", d);
   }
@@ -221,14 +223,20 @@ lbm_status refresh_args(lbm_batch* b) {
   return b->precision == LBM_FP64 ? upload_args<double>(b) : upload_args<float>(b);
 }
 
-template <class Lat, class T, bool LIN, bool O32>
-void launch_step_t(const lbm_batch* b, int grid, int flip, bool flux, hipStream_t st) {
+template <class Lat, class T, bool LIN, bool O32, bool PER>
+void launch_step_p(const lbm_batch* b, int grid, int flip, bool flux, hipStream_t st) {
   const dim3 block(kWave, kRows);
   const StepArgs<T>* a = (const StepArgs<T>*)b->args;
   if (flux)
-    k_step_batch<Lat, T, true, LIN, O32><<<grid, block, 0, st>>>(a, b->owner, flip);
+    k_step_batch<Lat, T, true, LIN, O32, PER><<<grid, block, 0, st>>>(a, b->owner, flip);
   else
-    k_step_batch<Lat, T, false, LIN, O32><<<grid, block, 0, st>>>(a, b->owner, flip);
+    k_step_batch<Lat, T, false, LIN, O32, PER><<<grid, block, 0, st>>>(a, b->owner, flip);
+}
+
+template <class Lat, class T, bool LIN, bool O32>
+void launch_step_t(const lbm_batch* b, int grid, int flip, bool flux, hipStream_t st) {
+  if (b->periodic) launch_step_p<Lat, T, LIN, O32, true>(b, grid, flip, flux, st);
+  else launch_step_p<Lat, T, LIN, O32, false>(b, grid, flip, flux, st);
 }
 
 template <class Lat, class T>
@@ -321,9 +329,20 @@ lbm_status pass_flux(lbm_batch* b) {
   return LBM_OK;
 }
 
+// Pass-flux results of every sample, lowered by its force offset (see
+// flux_pass_offset): the same arithmetic as the single-domain flux.
+lbm_status read_pass_q(lbm_batch* b, double* h);
+
 lbm_status read_q(lbm_batch* b, double* h) {
   HIP_TRY(hipMemcpyAsync(h, b->q, (size_t)b->n * sizeof(double), hipMemcpyDeviceToHost, b->stream));
   HIP_TRY(hipStreamSynchronize(b->stream));
+  return LBM_OK;
+}
+
+lbm_status read_pass_q(lbm_batch* b, double* h) {
+  lbm_status s = read_q(b, h);
+  if (s != LBM_OK) return s;
+  for (int d = 0; d < b->n; ++d) h[d] -= flux_pass_offset(b->ctx[d]);
   return LBM_OK;
 }
 
@@ -366,6 +385,7 @@ lbm_status lbm_batch_create(lbm_batch** out, int32_t n, lbm_ctx* const* ctxs, vo
   b->linear_eq = ctxs[0]->linear_eq;
   b->K = ctxs[0]->g.check_every;
   b->off32 = off32_ok(ctxs[0]);
+  b->periodic = ctxs[0]->g.boundary == LBM_BC_PERIODIC;
   b->stream = (hipStream_t)stream;
   b->arg_size = B.arg_size;
   uint8_t* w = (uint8_t*)work;
@@ -447,7 +467,7 @@ lbm_status lbm_batch_run_to_steady(lbm_batch* b, double tol, int64_t max_steps,
   s = pass_flux(b);
   if (s != LBM_OK) return s;
   std::vector<double> prev(n), q(n), resid(n, INFINITY);
-  s = read_q(b, prev.data());
+  s = read_pass_q(b, prev.data());
   if (s != LBM_OK) return s;
   std::vector<char> run(n);
   std::vector<int64_t> done(n, 0);   // steps taken in this call
@@ -540,7 +560,7 @@ lbm_status lbm_batch_flux(lbm_batch* b, double* q_out) {
   if (!b || !q_out) return fail(LBM_EINVAL, "NULL argument");
   lbm_status s = pass_flux(b);
   if (s != LBM_OK) return s;
-  s = read_q(b, q_out);
+  s = read_pass_q(b, q_out);
   if (s != LBM_OK) return s;
   for (int d = 0; d < b->n; ++d)
     if (!isfinite(q_out[d])) return fail(LBM_ENONFINITE, "sample %d: flux is not finite", d);
@@ -549,13 +569,17 @@ lbm_status lbm_batch_flux(lbm_batch* b, double* q_out) {
 
 lbm_status lbm_batch_permeability(lbm_batch* b, double* k_out, int32_t* status_out) {
   if (!b || !k_out) return fail(LBM_EINVAL, "NULL argument");
-  for (int d = 0; d < b->n; ++d)
-    if (b->ctx[d]->rho_in == b->ctx[d]->rho_out)
+  for (int d = 0; d < b->n; ++d) {
+    const lbm_ctx* c = b->ctx[d];
+    if (c->g.boundary == LBM_BC_PRESSURE && c->rho_in == c->rho_out)
       return fail(LBM_ESTATE, "sample %d: rho_in == rho_out: no pressure drop", d);
+    if (c->g.boundary == LBM_BC_PERIODIC && c->g.body_force == 0.0)
+      return fail(LBM_ESTATE, "sample %d: periodic case without a body force", d);
+  }
   lbm_status s = pass_flux(b);
   if (s != LBM_OK) return s;
   std::vector<double> q(b->n);
-  s = read_q(b, q.data());
+  s = read_pass_q(b, q.data());
   if (s != LBM_OK) return s;
   lbm_status first = LBM_OK;
   int first_d = -1;

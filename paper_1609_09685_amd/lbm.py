@@ -18,6 +18,8 @@ LBM_D2Q9, LBM_D3Q19 = 9, 19
 LBM_FP64, LBM_FP32 = 0, 1
 _PRECISION = {"fp64": LBM_FP64, "fp32": LBM_FP32}
 _START = {"uniform": 0, "linear": 1}
+LBM_BC_PRESSURE, LBM_BC_PERIODIC = 0, 1
+_BOUNDARY = {"pressure": LBM_BC_PRESSURE, "periodic": LBM_BC_PERIODIC}
 
 
 class LBMError(RuntimeError):
@@ -31,7 +33,8 @@ class Geom(ctypes.Structure):
     _fields_ = [("lattice", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
                 ("nz", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("check_every", ctypes.c_int32), ("rho0", ctypes.c_double),
-                ("n_fluid", ctypes.c_int64)]
+                ("n_fluid", ctypes.c_int64), ("boundary", ctypes.c_int32),
+                ("body_force", ctypes.c_double)]
 
 
 class Buffers(ctypes.Structure):
@@ -141,7 +144,11 @@ class Solver:
     """
 
     def __init__(self, mask, tau, rho_in, rho_out, precision="fp32", lattice=None,
-                 check_every=100, rho0=1.0, device="cuda", stream=None):
+                 check_every=100, rho0=1.0, device="cuda", stream=None, boundary="pressure",
+                 body_force=0.0):
+        """boundary: "pressure" (density at inlet / outlet ghost planes, symmetric
+        sides) or "periodic" (six periodic faces driven by the acceleration
+        body_force along x; rho_in = rho_out is then the starting density)."""
         import torch
 
         lib = load_library()
@@ -161,8 +168,10 @@ class Solver:
         self.D = 2 if self.lattice == LBM_D2Q9 else 3
         self.device = torch.device(device)
         self.n_fluid = int((m == 0).sum())
+        self.boundary, self.body_force = boundary, float(body_force)
         self._geom = Geom(self.lattice, self.nx, self.ny, self.nz, _PRECISION[precision],
-                          int(check_every), float(rho0), self.n_fluid)
+                          int(check_every), float(rho0), self.n_fluid, _BOUNDARY[boundary],
+                          self.body_force)
         fb, wb = ctypes.c_size_t(0), ctypes.c_size_t(0)
         _check(lib.lbm_query_sizes(ctypes.byref(self._geom), ctypes.byref(fb), ctypes.byref(wb)))
         self.f_bytes, self.work_bytes = fb.value, wb.value

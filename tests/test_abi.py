@@ -64,7 +64,10 @@ def _status(g):
                                 dict(precision=5), dict(check_every=0), dict(rho0=0.0),
                                 dict(rho0=float("nan")), dict(n_fluid=-1),
                                 dict(n_fluid=100 * 50 + 1),
-                                dict(lattice=19, nx=2048, ny=2048, nz=1025, n_fluid=2**32 + 5)])
+                                dict(lattice=19, nx=2048, ny=2048, nz=1025, n_fluid=2**32 + 5),
+                                dict(boundary=2), dict(boundary=-1),
+                                dict(boundary=1, body_force=float("inf")),
+                                dict(body_force=1e-5)])
 def test_query_sizes_rejects(kw):
     st, _, _ = _status(_geom(**kw))
     assert st == lbm.LBM_EINVAL
@@ -115,6 +118,11 @@ def test_init_validates_before_any_hip_call():
     odd = lbm.Buffers()
     odd.f[0], odd.f[1], odd.mask, odd.work = fake + 4, fake * 2, fake, fake * 4
     assert lib.lbm_init(ctypes.byref(h), ctypes.byref(g), ctypes.byref(odd), 0.8, 1.0, 1.0) == lbm.LBM_EINVAL
+    # periodic case: one density everywhere (no inlet / outlet)
+    gp = _geom(boundary=lbm.LBM_BC_PERIODIC, body_force=1e-5)
+    st = lib.lbm_init(ctypes.byref(h), ctypes.byref(gp), ctypes.byref(bufs), 0.8, 1.001, 0.999)
+    assert st == lbm.LBM_EINVAL and "periodic" in lib.lbm_last_error().decode()
+    assert not h.value
     assert lib.lbm_step(None, 1) == lbm.LBM_EINVAL
     assert lib.lbm_destroy(None) == lbm.LBM_OK
 

@@ -454,6 +454,11 @@ def test_periodic_force_momentum_budget():
         o.step(t - o.steps)
         # f-form populations ~ w_i: momentum sums carry ~ N Q ulp(1) of rounding
         assert abs(o.flux() - (t - 0.5) * F * 5 * 3) < 105 * 19 * 2.0 ** -52
+        # and node by node: rho = 1, u = (t - 1/2) F, the forcing scheme's velocity
+        rho, u = o.macro()
+        assert np.abs(rho - 1.0).max() < 19 * 2.0 ** -52
+        assert np.abs(u[..., 0] - (t - 0.5) * F).max() < 19 * 2.0 ** -52
+        assert np.abs(u[..., 1:]).max() < 19 * 2.0 ** -52
 
 
 def test_periodic_mass_conserved():
