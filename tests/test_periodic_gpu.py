@@ -13,7 +13,7 @@ import numpy as np
 import pytest
 
 import oracle
-from paper_1609_09685_amd import lbm
+from paper_1609_09685_amd import force_driven, lbm
 from paper_1609_09685_amd.qsgs import qsgs_2d, qsgs_3d
 
 from lbm_testutil import (field_floor, fields_match, from_oracle_f, random_state, state_view,
@@ -79,6 +79,40 @@ def test_d3q19_qsgs_fixed_steps(precision, linear_eq):
     assert abs(kg - ko) / ko <= TOL[precision], (kg, ko)
     ok, rel = fields_match(s, o, TOL[precision])
     assert ok, rel
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_inertial_regime_vs_oracle(precision):
+    """Small viscosity and a large force (tau = 0.51, g = 1e-4, pore Reynolds
+    number ~ 8 at steady state): the nonlinear equilibrium and forcing terms
+    carry weight; k and fields after 1500 steps."""
+    m = force_driven.medium(24, seed=2)
+    s, o = _pair(19, m, precision, 0.51, 1e-4)
+    s.step(1500)
+    o.step(1500)
+    kg, ko = s.permeability(), o.permeability()
+    assert abs(kg - ko) / ko <= TOL[precision], (kg, ko)
+    ok, rel = fields_match(s, o, TOL[precision])
+    assert ok, rel
+
+
+def test_fig5_inertia_and_linear_equilibrium():
+    """The paper's 3D finding (its Fig. 5) on a 48^3 medium of the paper's
+    porosity: with the full equilibrium, k for the large force falls below k
+    for the small one at small Kn (tau = 0.51) and not at tau = 1; with the
+    linear equilibrium both forces give the same k at both tau."""
+    m = force_driven.medium(48, seed=1)
+    rows, info = force_driven.sweep(m, taus=(0.51, 1.0), forces=(1e-6, 1e-4), tol=1e-8)
+    assert abs(info["porosity"] - force_driven.POROSITY) <= 1.0 / m.size   # one voxel
+    assert all(r["status"] == lbm.LBM_OK for r in rows), rows
+    k = {(r["linear"], r["tau"], r["g"]): r["k"] for r in rows}
+    ratio = {(lin, tau): k[(lin, tau, 1e-4)] / k[(lin, tau, 1e-6)]
+             for lin in (False, True) for tau in (0.51, 1.0)}
+    print(ratio)
+    assert ratio[(False, 0.51)] < 0.95
+    assert abs(ratio[(False, 1.0)] - 1) < 1e-5
+    assert abs(ratio[(True, 0.51)] - 1) < 1e-4
+    assert abs(ratio[(True, 1.0)] - 1) < 1e-5
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
