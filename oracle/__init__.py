@@ -57,6 +57,9 @@ def _load():
     lib.oracle_knudsen.restype = _d
     lib.oracle_set_periodic.argtypes = [_p, _i, _d, _d]
     lib.oracle_set_periodic.restype = _i
+    lib.oracle_set_trt.argtypes = [_p, _d]
+    lib.oracle_set_trt.restype = _i
+    lib.oracle_collide_trt.argtypes = [_i, _p, _d, _d, _i, _p]
     lib.oracle_set_threads.argtypes = [_i]
     lib.oracle_threads.restype = _i
     _lib = lib
@@ -101,6 +104,14 @@ def collide(Q, fin, tau, linear=False):
     return out
 
 
+def collide_trt(Q, fin, tau, magic, linear=False):
+    """One TRT collision of a node's populations fin (length Q), Lambda = magic."""
+    fin = np.ascontiguousarray(fin, dtype=np.float64)
+    out = np.zeros(Q)
+    _load().oracle_collide_trt(Q, _ptr(fin), float(tau), float(magic), int(linear), _ptr(out))
+    return out
+
+
 def knudsen(tau, nx):
     """Kn = sqrt(pi/6) (tau - 1/2) / Nx."""
     return float(_load().oracle_knudsen(float(tau), int(nx)))
@@ -126,10 +137,11 @@ class Oracle:
     """
 
     def __init__(self, Q, mask, tau, rho_in, rho_out, linear_eq=False, start="uniform",
-                 periodic=False, force=0.0, rho0=1.0):
+                 periodic=False, force=0.0, rho0=1.0, trt_magic=0.0):
         """periodic=True: six periodic faces and a body force of density `force`
         (= rho0 g) along x, the paper's 3D case; rho_in = rho_out is then the
-        starting density."""
+        starting density.  trt_magic > 0: two-relaxation-time collision with
+        Lambda = (tau - 1/2)(tau_minus - 1/2) = trt_magic (0: BGK)."""
         lib = _load()
         m = np.ascontiguousarray(mask, dtype=np.uint8)
         if m.ndim == 2:
@@ -146,6 +158,9 @@ class Oracle:
         self.periodic, self.force, self.rho0 = bool(periodic), float(force), float(rho0)
         if lib.oracle_set_periodic(self._h, int(self.periodic), self.force, self.rho0) != 0:
             raise ValueError("a body force needs the periodic case")
+        self.trt_magic = float(trt_magic)
+        if lib.oracle_set_trt(self._h, self.trt_magic) != 0:
+            raise ValueError("trt_magic must be >= 0")
         self.init_rest(start)
 
     def __del__(self):

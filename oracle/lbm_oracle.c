@@ -10,7 +10,9 @@
  * intrinsic permeability"):
  *   - single-relaxation-time (BGK) lattice Boltzmann with the normalised
  *     relaxation time tau and viscosity nu = (tau - 1/2)/3 in lattice units
- *     (Eq. 1 with c = dx = dt = 1);
+ *     (Eq. 1 with c = dx = dt = 1); optionally the two-relaxation-time
+ *     collision (TRT, Ginzburg), a multi-relaxation scheme of the kind the
+ *     paper names for a wider tau range;
  *   - the D2Q9 and D3Q19 lattices (Qian, d'Humieres & Lallemand 1992), which the
  *     paper uses for its 2D and 3D cases;
  *   - pressure-driven flow along x (Results, first paragraph): density imposed
@@ -49,6 +51,8 @@ typedef struct {
   int periodic;           /* 1: all six faces periodic (force-driven case) */
   double force;           /* body-force density along x, F = rho0 g (periodic case) */
   double rho0;            /* reference density of the force and of Eq. 2 */
+  int trt;                /* 1: two-relaxation-time collision */
+  double tau_minus;       /* TRT: relaxation time of the odd (antisymmetric) part */
   unsigned char *solid;   /* [nz][ny][nx], 1 = solid */
   double *f;              /* post-collision populations of the current step */
   double *tmp;
@@ -181,7 +185,13 @@ static double pulled(const oracle_t *o, int x, int y, int z, int i) {
  *   F_i = w_i [3 (c_i - u).F + 9 (c_i.u)(c_i.F)],
  * or F_i = 3 w_i c_i.F with the linear equilibrium (both linear in the
  * deviations from rest then). */
+static void collide_trt(const oracle_t *o, const double *fin, double *fout);
+
 static void collide(const oracle_t *o, const double *fin, double *fout) {
+  if (o->trt) {
+    collide_trt(o, fin, fout);
+    return;
+  }
   double rho, u[3];
   moments(o, fin, &rho, u);
   const double F = o->force;
@@ -200,6 +210,45 @@ static void collide(const oracle_t *o, const double *fin, double *fout) {
       }
       fout[i] += (1.0 - 0.5 / o->tau) * Fi;
     }
+  }
+}
+
+/* Two-relaxation-time collision (Ginzburg's TRT; the paper names
+ * multi-relaxation-time schemes as the way to a wider tau range).  Every
+ * population and its opposite direction split into a symmetric (even) and an
+ * antisymmetric (odd) half: x+_i = (x_i + x_opp(i))/2, x-_i = (x_i - x_opp(i))/2.
+ * The even non-equilibrium half relaxes with tau+ = tau (which sets the
+ * viscosity), the odd half with tau-; the magic parameter
+ * Lambda = (tau+ - 1/2)(tau- - 1/2) fixes the bounce-back wall position, so
+ * with Lambda held the steady solutions do not depend on tau.  The body force
+ * term of the BGK collision splits the same way, each half with its own
+ * (1 - 1/(2 tau+-)) factor.  Lambda = (tau - 1/2)^2 (tau- = tau) is BGK. */
+static void collide_trt(const oracle_t *o, const double *fin, double *fout) {
+  double rho, u[3];
+  moments(o, fin, &rho, u);
+  const double F = o->force;
+  if (F != 0.0) u[0] += 0.5 * F / rho;
+  double neq[QMAX], src[QMAX];
+  for (int i = 0; i < o->Q; ++i) {
+    neq[i] = fin[i] - o->w[i] * rho * poly(o, i, u);
+    src[i] = 0.0;
+    if (F != 0.0) {
+      double cx = o->c[i][0];
+      if (o->linear_eq) {
+        src[i] = 3.0 * o->w[i] * cx * F;
+      } else {
+        double cu = o->c[i][0] * u[0] + o->c[i][1] * u[1] + o->c[i][2] * u[2];
+        src[i] = o->w[i] * (3.0 * (cx - u[0]) * F + 9.0 * cu * cx * F);
+      }
+    }
+  }
+  const double tp = o->tau, tm = o->tau_minus;
+  for (int i = 0; i < o->Q; ++i) {
+    const int j = o->opp[i];
+    const double n_even = 0.5 * (neq[i] + neq[j]), n_odd = 0.5 * (neq[i] - neq[j]);
+    const double s_even = 0.5 * (src[i] + src[j]), s_odd = 0.5 * (src[i] - src[j]);
+    fout[i] = fin[i] - n_even / tp - n_odd / tm + (1.0 - 0.5 / tp) * s_even +
+              (1.0 - 0.5 / tm) * s_odd;
   }
 }
 
@@ -255,6 +304,16 @@ int oracle_set_periodic(oracle_t *o, int periodic, double force, double rho0) {
   o->periodic = periodic ? 1 : 0;
   o->force = force;
   o->rho0 = rho0;
+  return 0;
+}
+
+/* Collision model: magic > 0 selects TRT with Lambda = magic, i.e.
+ * tau- = 1/2 + magic / (tau - 1/2); magic = 0 returns to BGK.  Returns -1 for
+ * a negative or non-finite magic. */
+int oracle_set_trt(oracle_t *o, double magic) {
+  if (!(magic >= 0.0) || !isfinite(magic)) return -1;
+  o->trt = magic > 0.0;
+  o->tau_minus = o->trt ? 0.5 + magic / (o->tau - 0.5) : o->tau;
   return 0;
 }
 
@@ -417,6 +476,20 @@ void oracle_collide(int Q, const double *fin, double tau, int linear_eq, double 
   set_lattice(&o, Q);
   o.tau = tau;
   o.linear_eq = linear_eq;
+  collide(&o, fin, out);
+}
+
+/* One TRT collision of a node's populations (no force); magic as in
+ * oracle_set_trt (> 0). */
+void oracle_collide_trt(int Q, const double *fin, double tau, double magic, int linear_eq,
+                        double *out) {
+  oracle_t o;
+  memset(&o, 0, sizeof o);
+  set_lattice(&o, Q);
+  o.tau = tau;
+  o.linear_eq = linear_eq;
+  o.trt = 1;
+  o.tau_minus = 0.5 + magic / (tau - 0.5);
   collide(&o, fin, out);
 }
 
