@@ -73,7 +73,8 @@ def kernel_source_hash():
     """Short hash of the step kernel's sources, to tie profiled counters to them."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("kernels.h", "lattice.h", "context.h", "lbm_api.hip"):
+    for f in ("kernels.h", "lattice.h", "context.h", "step_launch.h", "step_launch.hip",
+              "lbm_api.hip"):
         with open(os.path.join(ROOT, "paper_1609_09685_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

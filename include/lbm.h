@@ -190,6 +190,18 @@ lbm_status lbm_get_slot_map(lbm_ctx *ctx, int32_t *map);
 /* Tuning and model options (LBM_OPT_*); take effect at the next step. */
 lbm_status lbm_set_option(lbm_ctx *ctx, int32_t option, int64_t value);
 
+/* Collision model.  magic > 0: two-relaxation-time collision (TRT,
+ * Ginzburg), a multi-relaxation scheme of the kind the paper names for a
+ * wider tau range (discussion of Fig. 2): for every direction and its
+ * opposite the even half of the non-equilibrium part relaxes with tau (the
+ * viscosity, Eq. 1) and the odd half with tau- = 1/2 + magic/(tau - 1/2), so
+ * that (tau - 1/2)(tau- - 1/2) = magic; the body-force term splits the same
+ * way.  With the magic parameter held the bounce-back wall position no longer
+ * moves with tau: a channel of H fluid rows has k = phi (H^2 - 1 + 8 magic)/12
+ * at every tau.  magic = 0: BGK (default).  Takes effect at the next step;
+ * LBM_EINVAL for a negative or non-finite magic. */
+lbm_status lbm_set_trt(lbm_ctx *ctx, double magic);
+
 /* Direction table of the internal order: c[3*Q] (x,y,z per direction) and
  * w[Q].  Q = 9 or 19. */
 lbm_status lbm_lattice(int32_t lattice, int32_t *c, double *w);
@@ -221,7 +233,8 @@ const char *lbm_version(void);
  * samples one by one (same tiles, same deterministic reductions).
  *
  * Requirements: 1 <= n samples, all with the same lattice, precision,
- * check_every, boundary case and linear-equilibrium option, all on the batch's stream (the
+ * check_every, boundary case, collision model (BGK or TRT; the magic
+ * parameters may differ) and linear-equilibrium option, all on the batch's stream (the
  * stream given to lbm_batch_create).  While a batch exists its contexts may
  * still be used directly (on that stream), but their tile-order options must
  * not change.  Convergence: after every window of K = check_every steps the

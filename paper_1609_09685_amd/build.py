@@ -18,8 +18,10 @@ QSGS_LIB = os.path.join(PKG, "libqsgs.so")
 LBM_LIB = os.path.join(PKG, "liblbm.so")
 ARCH = "gfx950"
 
-# Sources of liblbm.so, compiled together as one translation unit list.
+# Sources of liblbm.so, each compiled to an object of its own.
 LBM_SOURCES = ["lbm_api.hip", "lbm_batch.hip", "wsn_api.hip"]
+# The step-kernel launchers, one object per (lattice, precision) pair.
+STEP_PAIRS = [("D2Q9", "float"), ("D2Q9", "double"), ("D3Q19", "float"), ("D3Q19", "double")]
 
 HIPCC_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
@@ -50,9 +52,12 @@ def build_lbm(verbose=False):
     compile_flags = [f for f in HIPCC_FLAGS if f != "-shared"]
     procs = []
     objs = []
-    for src in LBM_SOURCES:
-        obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
-        cmd = ["hipcc", *compile_flags, f"-I{INCLUDE}", f"-I{CSRC}", "-c", "-o", obj,
+    jobs = [(src, os.path.splitext(src)[0], []) for src in LBM_SOURCES]
+    jobs += [("step_launch.hip", f"step_{lat}_{real}", [f"-DLBM_LAT={lat}", f"-DLBM_REAL={real}"])
+             for lat, real in STEP_PAIRS]
+    for src, name, defs in jobs:
+        obj = os.path.join(objdir, name + ".o")
+        cmd = ["hipcc", *compile_flags, *defs, f"-I{INCLUDE}", f"-I{CSRC}", "-c", "-o", obj,
                os.path.join(CSRC, src)]
         if verbose:
             print(" ".join(cmd), flush=True)

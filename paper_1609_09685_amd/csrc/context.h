@@ -65,6 +65,7 @@ struct lbm_ctx {
   int xcd_remap;
   uint64_t n_slots;    // slots in use per direction array (fluid nodes + padding)
   int band;            // 0 or tile rows per band (banded tile order)
+  double trt_magic;    // > 0: TRT collision with this magic parameter; 0: BGK
 
   uint64_t* bits() const { return (uint64_t*)(work + L.off_bits); }
   uint32_t* pfx() const { return (uint32_t*)(work + L.off_pfx); }
@@ -148,6 +149,14 @@ StepArgs<T> step_args(const lbm_ctx* c) {
   a.dv_band_plane = make_fastdiv((uint32_t)(a.band > 0 ? a.band * a.tiles_x : 1));
   a.fx = force_density<T>(c);
   a.omega = (T)(1.0 / c->tau);
+  {
+    // TRT: tau- from the magic parameter (tau+ - 1/2)(tau- - 1/2); BGK: tau- = tau
+    const double wp = 1.0 / c->tau;
+    const double wm = c->trt_magic > 0.0 ? 1.0 / (0.5 + c->trt_magic / (c->tau - 0.5)) : wp;
+    a.omega_m = (T)wm;
+    a.trt_a = (T)(0.5 * (wp + wm));
+    a.trt_b = (T)(0.5 * (wp - wm));
+  }
   a.rho0 = (T)c->g.rho0;
   a.drho_in = (T)(c->rho_in - c->g.rho0);
   a.drho_out = (T)(c->rho_out - c->g.rho0);

@@ -137,6 +137,8 @@ struct StepArgs {
   FastDiv dv_band_blocks, dv_band_plane;   // nz * band * tiles_x, band * tiles_x
   T omega, rho0, drho_in, drho_out;  // 1/tau; rho0; rho_in - rho0; rho_out - rho0
   T fx;                            // body-force density along x (rho0 g), periodic case
+  T omega_m;                       // TRT: 1/tau- (odd part); omega otherwise
+  T trt_a, trt_b;                  // TRT: (omega +- omega_m) / 2
 };
 
 // ---------------------------------------------------------------- reductions
@@ -353,7 +355,7 @@ struct RowWords {
 // lds_base = the block-local position of the segment minus its first slot).
 // Returns the node's x-momentum rho u_x (with a body force, j_x + F/2; 0 if
 // the node is not fluid).
-template <class L, class T, bool LINEAR, bool OFF32, bool PER, bool YZE, bool XE>
+template <class L, class T, bool LINEAR, bool OFF32, bool PER, bool TRT, bool YZE, bool XE>
 __device__ __forceinline__ T node_update(const StepArgs<T>& a, int y, int z, int w, int lane,
                                          T (*out)[kThreads], uint32_t lds_base) {
   const int x = (w << 6) + lane;
@@ -537,7 +539,39 @@ __device__ __forceinline__ T node_update(const StepArgs<T>& a, int y, int z, int
     uz = jz * inv;
   }
   const T usq15 = T(1.5) * (ux * ux + uy * uy + uz * uz);
-  if constexpr (!PER) {
+  if constexpr (TRT) {
+    // Two relaxation times: the non-equilibrium n = g - g_eq of a direction
+    // and of its opposite split into an even half, relaxed with omega, and an
+    // odd half, relaxed with omega_m; per direction that is
+    // g' = g - a n_i - b n_opp(i), a, b = (omega +- omega_m)/2.  The force
+    // term splits the same way: its odd half is 3 w_i c_ix F, its even half
+    // w_i (9 c_ix (c_i.u) - 3 u_x) F (absent with the linear equilibrium),
+    // each with its own (1 - omega/2) factor.
+    T nq[L::Q];
+    unroll<0, L::Q>([&](auto qc) {
+      constexpr int q = decltype(qc)::value;
+      nq[q] = g[q] - geq<L, q, LINEAR>(drho, rho, ux, uy, uz, usq15);
+    });
+    T af_even = T(0), af_odd = T(0);
+    if constexpr (PER) {
+      af_even = (T(1) - T(0.5) * a.omega) * a.fx;
+      af_odd = (T(1) - T(0.5) * a.omega_m) * a.fx;
+    }
+    unroll<0, L::Q>([&](auto qc) {
+      constexpr int q = decltype(qc)::value;
+      constexpr int cx = L::cx[q];
+      T v = g[q] - a.trt_a * nq[q] - a.trt_b * nq[L::opp[q]];
+      if constexpr (PER) {
+        if constexpr (cx != 0) v += T(3 * cx) * T(L::w[q]) * af_odd;
+        if constexpr (!LINEAR) {
+          const T cu = dot_c<L, q>(ux, uy, uz);
+          v += T(L::w[q]) * af_even * (T(9 * cx) * cu - T(3) * ux);
+        }
+      }
+      out[q][lds_base + self] = v;
+      g[q] = v;
+    });
+  } else if constexpr (!PER) {
     unroll<0, L::Q>([&](auto qc) {
       constexpr int q = decltype(qc)::value;
       const T ge = geq<L, q, LINEAR>(drho, rho, ux, uy, uz, usq15);
@@ -581,17 +615,17 @@ __device__ __forceinline__ T node_update(const StepArgs<T>& a, int y, int z, int
 }
 
 // Picks the specialisation of node_update for a wave's (y, z, w).
-template <class L, class T, bool LINEAR, bool OFF32, bool PER>
+template <class L, class T, bool LINEAR, bool OFF32, bool PER, bool TRT>
 __device__ __forceinline__ T wave_update(const StepArgs<T>& a, int y, int z, int w, int lane,
                                          T (*out)[kThreads], uint32_t lds_base) {
   const bool yze = y == 0 || y == a.ny - 1 || (L::D == 3 && (z == 0 || z == a.nz - 1));
   const bool xe = w == 0 || w == ((a.nx - 1) >> 6);
   if (yze) {
-    if (xe) return node_update<L, T, LINEAR, OFF32, PER, true, true>(a, y, z, w, lane, out, lds_base);
-    return node_update<L, T, LINEAR, OFF32, PER, true, false>(a, y, z, w, lane, out, lds_base);
+    if (xe) return node_update<L, T, LINEAR, OFF32, PER, TRT, true, true>(a, y, z, w, lane, out, lds_base);
+    return node_update<L, T, LINEAR, OFF32, PER, TRT, true, false>(a, y, z, w, lane, out, lds_base);
   }
-  if (xe) return node_update<L, T, LINEAR, OFF32, PER, false, true>(a, y, z, w, lane, out, lds_base);
-  return node_update<L, T, LINEAR, OFF32, PER, false, false>(a, y, z, w, lane, out, lds_base);
+  if (xe) return node_update<L, T, LINEAR, OFF32, PER, TRT, false, true>(a, y, z, w, lane, out, lds_base);
+  return node_update<L, T, LINEAR, OFF32, PER, TRT, false, false>(a, y, z, w, lane, out, lds_base);
 }
 
 // Order in which tiles meet the hardware.  The dispatcher deals block ids
@@ -629,7 +663,7 @@ __device__ __forceinline__ int logical_block(int hw, const StepArgs<T>& a) {
 // zero).  FLUX: each wave also stores the FP64 sum of its 64 nodes'
 // x-momentum at the index of its bitmap word, (z ny + y) nw + w, so the flux
 // does not depend on the tiling.
-template <class L, class T, bool FLUX, bool LINEAR, bool OFF32, bool PER>
+template <class L, class T, bool FLUX, bool LINEAR, bool OFF32, bool PER, bool TRT>
 __device__ __forceinline__ void step_tile(const StepArgs<T>& a, const uint32_t hw) {
   __shared__ T out[L::Q][kThreads];
   __shared__ uint32_t seg_first[kRows], seg_count[kRows];
@@ -680,7 +714,7 @@ __device__ __forceinline__ void step_tile(const StepArgs<T>& a, const uint32_t h
   T jx = T(0);
   if (row_ok && w < a.nw) {
     const uint32_t lds_base = (uint32_t)(j * S * kWave) - first;
-    jx = wave_update<L, T, LINEAR, OFF32, PER>(a, y, z, w, lane, out, lds_base);
+    jx = wave_update<L, T, LINEAR, OFF32, PER, TRT>(a, y, z, w, lane, out, lds_base);
   }
   if constexpr (FLUX) {
     if (row_ok && w < a.nw) {
@@ -714,9 +748,9 @@ __device__ __forceinline__ void step_tile(const StepArgs<T>& a, const uint32_t h
   }
 }
 
-template <class L, class T, bool FLUX, bool LINEAR, bool OFF32, bool PER>
+template <class L, class T, bool FLUX, bool LINEAR, bool OFF32, bool PER, bool TRT>
 __global__ __launch_bounds__(kThreads) void k_step(const StepArgs<T> a) {
-  step_tile<L, T, FLUX, LINEAR, OFF32, PER>(a, blockIdx.x);
+  step_tile<L, T, FLUX, LINEAR, OFF32, PER, TRT>(a, blockIdx.x);
 }
 
 // One time step of many domains in one launch.  Block b runs block owner[b].y
@@ -726,13 +760,13 @@ __global__ __launch_bounds__(kThreads) void k_step(const StepArgs<T> a) {
 // owner[b].y of the domain's own launch would: the tile orders carry over.
 // args[2 d + flip] holds the arguments of domain d for this step (the two
 // entries of a domain differ by the ping-pong parity).
-template <class L, class T, bool FLUX, bool LINEAR, bool OFF32, bool PER>
+template <class L, class T, bool FLUX, bool LINEAR, bool OFF32, bool PER, bool TRT>
 __global__ __launch_bounds__(kThreads) void k_step_batch(const StepArgs<T>* __restrict__ args,
                                                          const int2* __restrict__ owner, int flip) {
   const int2 o = owner[blockIdx.x];
   if (o.x < 0) return;   // whole block
   const StepArgs<T> a = args[2 * o.x + flip];
-  step_tile<L, T, FLUX, LINEAR, OFF32, PER>(a, (uint32_t)o.y);
+  step_tile<L, T, FLUX, LINEAR, OFF32, PER, TRT>(a, (uint32_t)o.y);
 }
 
 // ------------------------------------------------------------ set-up kernels

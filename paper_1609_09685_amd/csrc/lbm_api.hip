@@ -19,6 +19,7 @@
 #include <new>
 
 #include "context.h"
+#include "step_launch.h"
 
 using namespace lbm;
 
@@ -129,33 +130,14 @@ lbm_status make_layout(const lbm_geom* g, Layout* L) {
   return LBM_OK;
 }
 
-// The pressure and periodic cases are separate instantiations, so the
-// pressure kernel carries none of the periodic code (registers, occupancy).
-template <class Lat, class T, bool FLUX, bool LIN, bool O32>
-void launch_k_step(const StepArgs<T>& a, int grid, dim3 block, hipStream_t st, bool per) {
-  if (per) k_step<Lat, T, FLUX, LIN, O32, true><<<grid, block, 0, st>>>(a);
-  else k_step<Lat, T, FLUX, LIN, O32, false><<<grid, block, 0, st>>>(a);
-}
-
 template <class Lat, class T>
 lbm_status launch_steps(lbm_ctx* c, int64_t n, bool flux_last) {
-  const dim3 block(kWave, kRows);
+  StepVariant v{false, c->linear_eq != 0, off32_ok(c), c->g.boundary == LBM_BC_PERIODIC,
+                c->trt_magic > 0.0};
   for (int64_t s = 0; s < n; ++s) {
     StepArgs<T> a = step_args<T>(c);
-    const int grid = step_grid(c, a);
-    const bool flux = flux_last && s == n - 1;
-    const int variant = (flux ? 1 : 0) | (c->linear_eq ? 2 : 0) | (off32_ok(c) ? 4 : 0);
-    const bool per = c->g.boundary == LBM_BC_PERIODIC;
-    switch (variant) {
-      case 0: launch_k_step<Lat, T, false, false, false>(a, grid, block, c->stream, per); break;
-      case 1: launch_k_step<Lat, T, true, false, false>(a, grid, block, c->stream, per); break;
-      case 2: launch_k_step<Lat, T, false, true, false>(a, grid, block, c->stream, per); break;
-      case 3: launch_k_step<Lat, T, true, true, false>(a, grid, block, c->stream, per); break;
-      case 4: launch_k_step<Lat, T, false, false, true>(a, grid, block, c->stream, per); break;
-      case 5: launch_k_step<Lat, T, true, false, true>(a, grid, block, c->stream, per); break;
-      case 6: launch_k_step<Lat, T, false, true, true>(a, grid, block, c->stream, per); break;
-      default: launch_k_step<Lat, T, true, true, true>(a, grid, block, c->stream, per); break;
-    }
+    v.flux = flux_last && s == n - 1;
+    launch_step_kernel<Lat, T>(a, step_grid(c, a), c->stream, v);
     c->parity ^= 1;
     c->steps += 1;
   }
@@ -400,6 +382,7 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_geom* geom, const lbm_buffers* bufs
   c->xcd_remap = 1;
   c->n_slots = 0;
   c->band = 16;
+  c->trt_magic = 0.0;
 
   auto fail_free = [&](lbm_status st) { delete c; return st; };
   s = build_fluid_map(c);
@@ -552,6 +535,14 @@ lbm_status lbm_set_option(lbm_ctx* c, int32_t option, int64_t value) {
     default:
       return fail(LBM_EINVAL, "unknown option %d", option);
   }
+}
+
+lbm_status lbm_set_trt(lbm_ctx* c, double magic) {
+  if (!c) return fail(LBM_EINVAL, "ctx is NULL");
+  if (!(magic >= 0.0) || !isfinite(magic))
+    return fail(LBM_EINVAL, "the TRT magic parameter must be >= 0 and finite, got %g", magic);
+  c->trt_magic = magic;
+  return ok();
 }
 
 lbm_status lbm_get_slot_map(lbm_ctx* c, int32_t* map) {

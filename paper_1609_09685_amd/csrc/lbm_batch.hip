@@ -26,6 +26,7 @@
 #include <vector>
 
 #include "context.h"
+#include "step_launch.h"
 
 using namespace lbm;
 using namespace lbm::host;
@@ -34,7 +35,7 @@ struct lbm_batch {
   int n;
   std::vector<lbm_ctx*> ctx;
   int lattice, precision, linear_eq, K;
-  bool off32, periodic;
+  bool off32, periodic, trt;
   hipStream_t stream;
   size_t arg_size;
   // device tables
@@ -98,6 +99,8 @@ lbm_status validate_ctxs(int32_t n, lbm_ctx* const* ctxs) {
       return fail(LBM_EINVAL, "sample %d: the linear-equilibrium option must match sample 0", d);
     if (c->g.boundary != c0->g.boundary)
       return fail(LBM_EINVAL, "sample %d: boundary case must match sample 0", d);
+    if ((c->trt_magic > 0.0) != (c0->trt_magic > 0.0))
+      return fail(LBM_EINVAL, "sample %d: collision model (BGK / TRT) must match sample 0", d);
     if (off32_ok(c) != off32_ok(c0))
       return fail(LBM_EINVAL, "sample %d: sizes too different to share one step kernel", d);
   }
@@ -203,6 +206,8 @@ lbm_status upload_args(lbm_batch* b) {
     lbm_ctx* c = b->ctx[d];
     if (c->linear_eq != b->linear_eq)
       return fail(LBM_ESTATE, "sample %d: the linear-equilibrium option changed", d);
+    if ((c->trt_magic > 0.0) != b->trt)
+      return fail(LBM_ESTATE, "sample %d: the collision model changed", d);
     const int p = c->parity;
     for (int j = 0; j < 2; ++j) {
       c->parity = p ^ j;
@@ -223,41 +228,23 @@ lbm_status refresh_args(lbm_batch* b) {
   return b->precision == LBM_FP64 ? upload_args<double>(b) : upload_args<float>(b);
 }
 
-template <class Lat, class T, bool LIN, bool O32, bool PER>
-void launch_step_p(const lbm_batch* b, int grid, int flip, bool flux, hipStream_t st) {
-  const dim3 block(kWave, kRows);
-  const StepArgs<T>* a = (const StepArgs<T>*)b->args;
-  if (flux)
-    k_step_batch<Lat, T, true, LIN, O32, PER><<<grid, block, 0, st>>>(a, b->owner, flip);
-  else
-    k_step_batch<Lat, T, false, LIN, O32, PER><<<grid, block, 0, st>>>(a, b->owner, flip);
-}
-
-template <class Lat, class T, bool LIN, bool O32>
-void launch_step_t(const lbm_batch* b, int grid, int flip, bool flux, hipStream_t st) {
-  if (b->periodic) launch_step_p<Lat, T, LIN, O32, true>(b, grid, flip, flux, st);
-  else launch_step_p<Lat, T, LIN, O32, false>(b, grid, flip, flux, st);
-}
-
-template <class Lat, class T>
-void launch_step_lt(const lbm_batch* b, int grid, int flip, bool flux, hipStream_t st) {
-  if (b->linear_eq) {
-    if (b->off32) launch_step_t<Lat, T, true, true>(b, grid, flip, flux, st);
-    else launch_step_t<Lat, T, true, false>(b, grid, flip, flux, st);
-  } else {
-    if (b->off32) launch_step_t<Lat, T, false, true>(b, grid, flip, flux, st);
-    else launch_step_t<Lat, T, false, false>(b, grid, flip, flux, st);
-  }
-}
-
 void launch_step(const lbm_batch* b, int grid, int flip, bool flux, hipStream_t st) {
   if (grid <= 0) return;
+  const StepVariant v{flux, b->linear_eq != 0, b->off32, b->periodic, b->trt};
   if (b->lattice == LBM_D2Q9) {
-    if (b->precision == LBM_FP64) launch_step_lt<D2Q9, double>(b, grid, flip, flux, st);
-    else launch_step_lt<D2Q9, float>(b, grid, flip, flux, st);
+    if (b->precision == LBM_FP64)
+      launch_batch_step_kernel<D2Q9, double>((const StepArgs<double>*)b->args, b->owner, flip,
+                                             grid, st, v);
+    else
+      launch_batch_step_kernel<D2Q9, float>((const StepArgs<float>*)b->args, b->owner, flip,
+                                            grid, st, v);
   } else {
-    if (b->precision == LBM_FP64) launch_step_lt<D3Q19, double>(b, grid, flip, flux, st);
-    else launch_step_lt<D3Q19, float>(b, grid, flip, flux, st);
+    if (b->precision == LBM_FP64)
+      launch_batch_step_kernel<D3Q19, double>((const StepArgs<double>*)b->args, b->owner, flip,
+                                              grid, st, v);
+    else
+      launch_batch_step_kernel<D3Q19, float>((const StepArgs<float>*)b->args, b->owner, flip,
+                                             grid, st, v);
   }
 }
 
@@ -386,6 +373,7 @@ lbm_status lbm_batch_create(lbm_batch** out, int32_t n, lbm_ctx* const* ctxs, vo
   b->K = ctxs[0]->g.check_every;
   b->off32 = off32_ok(ctxs[0]);
   b->periodic = ctxs[0]->g.boundary == LBM_BC_PERIODIC;
+  b->trt = ctxs[0]->trt_magic > 0.0;
   b->stream = (hipStream_t)stream;
   b->arg_size = B.arg_size;
   uint8_t* w = (uint8_t*)work;

@@ -62,6 +62,7 @@ _SIGS = {
     "lbm_get_populations": (_c.c_int, [_c.c_void_p, _c.c_void_p]),
     "lbm_set_populations": (_c.c_int, [_c.c_void_p, _c.c_void_p]),
     "lbm_set_option": (_c.c_int, [_c.c_void_p, _c.c_int32, _c.c_int64]),
+    "lbm_set_trt": (_c.c_int, [_c.c_void_p, _c.c_double]),
     "lbm_get_slot_map": (_c.c_int, [_c.c_void_p, _c.c_void_p]),
     "lbm_lattice": (_c.c_int, [_c.c_int32, _c.c_void_p, _c.c_void_p]),
     "lbm_steps": (_c.c_int, [_c.c_void_p, _c.POINTER(_c.c_int64)]),
@@ -205,6 +206,12 @@ class Solver:
 
     def set_linear_equilibrium(self, on=True):
         self.set_option(LBM_OPT_LINEAR_EQ, 1 if on else 0)
+
+    def set_trt(self, magic=3.0 / 16.0):
+        """Two-relaxation-time collision with the magic parameter
+        (tau - 1/2)(tau_minus - 1/2) = magic; magic = 0 returns to BGK."""
+        _check(self._lib.lbm_set_trt(self._h, float(magic)))
+        self.trt_magic = float(magic)
 
     def set_xcd_remap(self, mode=1):
         """Tile order over the XCDs: 0 hardware, 1 contiguous eighths, m >= 2 chunks of

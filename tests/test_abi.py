@@ -124,6 +124,7 @@ def test_init_validates_before_any_hip_call():
     assert st == lbm.LBM_EINVAL and "periodic" in lib.lbm_last_error().decode()
     assert not h.value
     assert lib.lbm_step(None, 1) == lbm.LBM_EINVAL
+    assert lib.lbm_set_trt(None, 0.1875) == lbm.LBM_EINVAL
     assert lib.lbm_destroy(None) == lbm.LBM_OK
 
 
