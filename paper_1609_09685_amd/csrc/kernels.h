@@ -572,11 +572,29 @@ __device__ __forceinline__ T node_update(const StepArgs<T>& a, int y, int z, int
       g[q] = v;
     });
   } else if constexpr (!PER) {
-    unroll<0, L::Q>([&](auto qc) {
-      constexpr int q = decltype(qc)::value;
-      const T ge = geq<L, q, LINEAR>(drho, rho, ux, uy, uz, usq15);
-      g[q] = g[q] - a.omega * (g[q] - ge);
+    // BGK, g' = (1 - omega) g + omega g_eq.  A direction and its opposite
+    // share the even part of the equilibrium, A = drho + rho (9/2 (c.u)^2 -
+    // 3/2 u.u), and differ in the sign of the odd part, B = 3 rho (c.u):
+    // g_eq = w (A + B) and w (A - B).
+    const T om = a.omega, om1 = T(1) - a.omega, rho3 = T(3) * rho;
+    {
+      T A0 = drho;
+      if constexpr (!LINEAR) A0 = drho - rho * usq15;
+      g[0] = om1 * g[0] + (om * T(L::w[0])) * A0;
+      out[0][lds_base + self] = g[0];
+    }
+    unroll<0, (L::Q - 1) / 2>([&](auto pc) {
+      constexpr int q = 1 + 2 * decltype(pc)::value, o = q + 1;
+      static_assert(L::opp[q] == o && L::w[q] == L::w[o], "opposite pairs (q, q + 1)");
+      const T cu = dot_c<L, q>(ux, uy, uz);
+      T A = drho;
+      if constexpr (!LINEAR) A = drho + rho * (T(4.5) * (cu * cu) - usq15);
+      const T ow = om * T(L::w[q]);
+      const T wA = ow * A, wB = ow * (rho3 * cu);
+      g[q] = om1 * g[q] + (wA + wB);
+      g[o] = om1 * g[o] + (wA - wB);
       out[q][lds_base + self] = g[q];
+      out[o][lds_base + self] = g[o];
     });
   } else {
     // forcing term (1 - omega/2) F_i, F_i = w_i [3 (c_i - u).F + 9 (c_i.u)(c_i.F)],
@@ -748,8 +766,17 @@ __device__ __forceinline__ void step_tile(const StepArgs<T>& a, const uint32_t h
   }
 }
 
+// Waves per SIMD the step kernels ask the register allocator for: the
+// single-domain FP32 pressure-driven BGK kernels fit 8 (the LDS limit) by
+// moving scalar values into vector lanes; the others (FP64, periodic, TRT,
+// and the batch kernels, which read their arguments from memory) would spill
+// to scratch and keep the allocator's own choice.
+template <class T, bool PER, bool TRT>
+constexpr int step_min_waves() { return sizeof(T) == 4 && !PER && !TRT ? 8 : 1; }
+
 template <class L, class T, bool FLUX, bool LINEAR, bool OFF32, bool PER, bool TRT>
-__global__ __launch_bounds__(kThreads) void k_step(const StepArgs<T> a) {
+__global__ __launch_bounds__(kThreads) __attribute__((
+    amdgpu_waves_per_eu(step_min_waves<T, PER, TRT>()))) void k_step(const StepArgs<T> a) {
   step_tile<L, T, FLUX, LINEAR, OFF32, PER, TRT>(a, blockIdx.x);
 }
 
