@@ -131,22 +131,37 @@ def main(argv=None):
     ap.add_argument("--precision", default="fp32", choices=("fp32", "fp64"))
     ap.add_argument("--tol", type=float, default=1e-9)
     ap.add_argument("--taus", type=float, nargs="*", default=list(TAUS))
+    ap.add_argument("--kn-steps", type=float, nargs="*", default=list(KN_STEPS),
+                    help="extra taus 1/2 + r d at refinement r (equal-Kn runs); none: only --taus")
+    ap.add_argument("--refine", type=int, nargs="*", default=list(REFINE))
+    ap.add_argument("--seeds", type=int, nargs="*", default=None,
+                    help="several structures (default: --seed)")
+    ap.add_argument("--porosity", type=float, default=POROSITY)
     ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
 
     def log(msg):
         print(msg, flush=True)
 
-    masks = media(a.nx, a.ny, seed=a.seed)
-    rows = sweep(masks, REFINE, a.taus, KN_STEPS, a.precision, a.tol, log=log)
-    c = collapse(rows, a.taus)
-    log("k/k_int spread between resolutions at equal tau: "
-        + ", ".join(f"{t}: {v:.3g}" for t, v in sorted(c["spread_equal_tau"].items())))
-    log("at equal Kn (tau - 1/2 = r d): "
-        + ", ".join(f"d={d}: {v:.3g}" for d, v in sorted(c["spread_equal_kn"].items())))
+    seeds = a.seeds if a.seeds else [a.seed]
+    rows = []
+    for seed in seeds:
+        masks = media(a.nx, a.ny, porosity=a.porosity, seed=seed, refine=a.refine)
+        log(f"structure seed {seed}, porosity {1 - masks[0].mean():.4f}, {a.precision}")
+        part = sweep(masks, a.refine, a.taus, a.kn_steps, a.precision, a.tol, log=log)
+        for r in part:
+            r["seed"] = seed
+        rows += part
+    c = None
+    if len(a.refine) > 1 and len(seeds) == 1:
+        c = collapse(rows, a.taus, a.kn_steps)
+        log("k/k_int spread between resolutions at equal tau: "
+            + ", ".join(f"{t}: {v:.3g}" for t, v in sorted(c["spread_equal_tau"].items())))
+        log("at equal Kn (tau - 1/2 = r d): "
+            + ", ".join(f"d={d}: {v:.3g}" for d, v in sorted(c["spread_equal_kn"].items())))
     if a.out:
         with open(a.out, "w") as f:
-            json.dump(dict(seed=a.seed, precision=a.precision, tol=a.tol, rows=rows,
+            json.dump(dict(seeds=seeds, precision=a.precision, tol=a.tol, rows=rows,
                            collapse=c), f, indent=1)
     return 0
 
