@@ -152,6 +152,10 @@ class Solver:
         body_force along x; rho_in = rho_out is then the starting density)."""
         import torch
 
+        if precision not in _PRECISION:
+            raise ValueError(f"precision must be one of {sorted(_PRECISION)}, got {precision!r}")
+        if boundary not in _BOUNDARY:
+            raise ValueError(f"boundary must be one of {sorted(_BOUNDARY)}, got {boundary!r}")
         lib = load_library()
         if not torch.cuda.is_available():
             raise RuntimeError("the lattice Boltzmann solver needs a GPU (HIP device)")
@@ -170,6 +174,7 @@ class Solver:
         self.device = torch.device(device)
         self.n_fluid = int((m == 0).sum())
         self.boundary, self.body_force = boundary, float(body_force)
+        self.trt_magic = 0.0
         self._geom = Geom(self.lattice, self.nx, self.ny, self.nz, _PRECISION[precision],
                           int(check_every), float(rho0), self.n_fluid, _BOUNDARY[boundary],
                           self.body_force)

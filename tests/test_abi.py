@@ -159,6 +159,14 @@ def test_solver_refuses_without_gpu():
         lbm.Solver(np.zeros((4, 8), np.uint8), 0.8, 1.001, 0.999)
 
 
+def test_solver_rejects_unknown_names():
+    """Bad option strings fail before any GPU or library work."""
+    with pytest.raises(ValueError):
+        lbm.Solver(np.zeros((4, 8), np.uint8), 0.8, 1.001, 0.999, precision="fp16")
+    with pytest.raises(ValueError):
+        lbm.Solver(np.zeros((4, 8), np.uint8), 0.8, 1.0, 1.0, boundary="wall")
+
+
 def test_batch_entry_points_validate():
     """Batch calls reject empty or NULL arguments before touching the device."""
     lib = lbm.load_library()

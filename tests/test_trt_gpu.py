@@ -174,6 +174,23 @@ def test_batch_rejects_mixed_collision_models():
         lbm.Batch([a, b])
 
 
+def test_batch_refuses_collision_change():
+    """Switching a sample between BGK and TRT after the batch was built is an
+    error (the batch launches one collision model); changing the magic
+    parameter of a TRT sample is not."""
+    a = lbm.Solver(qsgs_2d(64, 20, 0.7, 0), 0.8, 1.0005, 0.9995, lattice=9)
+    b = lbm.Solver(qsgs_2d(64, 20, 0.7, 1), 0.8, 1.0005, 0.9995, lattice=9)
+    a.set_trt(MAGIC)
+    b.set_trt(MAGIC)
+    batch = lbm.Batch([a, b])
+    batch.step(2)
+    b.set_trt(0.25)
+    batch.step(2)
+    b.set_trt(0.0)
+    with pytest.raises(lbm.LBMError):
+        batch.step(2)
+
+
 def test_trt_errors():
     s = lbm.Solver(qsgs_2d(64, 20, 0.7, 0), 0.8, 1.0005, 0.9995, lattice=9)
     for bad in (-1.0, float("nan"), float("inf")):
