@@ -260,9 +260,20 @@ __global__ __launch_bounds__(kBlock) void k_sum_splits(const float* __restrict__
                                                        size_t n, float* __restrict__ out) {
   const size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x;
   if (e >= n) return;
-  float s = 0.f;
-  for (int k = 0; k < nsplit; ++k) s += part[(size_t)k * n + e];
-  out[e] = s;
+  // four accumulators (split k into k % 4), so that the loads overlap;
+  // added in a fixed order, the result does not depend on the schedule
+  float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+  int k = 0;
+  for (; k + 3 < nsplit; k += 4) {
+    s0 += part[(size_t)k * n + e];
+    s1 += part[(size_t)(k + 1) * n + e];
+    s2 += part[(size_t)(k + 2) * n + e];
+    s3 += part[(size_t)(k + 3) * n + e];
+  }
+  if (k < nsplit) s0 += part[(size_t)k * n + e];
+  if (k + 1 < nsplit) s1 += part[(size_t)(k + 1) * n + e];
+  if (k + 2 < nsplit) s2 += part[(size_t)(k + 2) * n + e];
+  out[e] = (s0 + s1) + (s2 + s3);
 }
 
 // Column sums of g [npix][c] over pixel ranges of `sp` pixels into partial
@@ -278,10 +289,20 @@ __global__ __launch_bounds__(kBlock) void k_colsum_part(const float* __restrict_
   const int t = threadIdx.x;
   const int grp = t / cc, ch = t % cc;
   const int p_begin = blockIdx.x * sp, p_end = min(p_begin + sp, npix);
-  float v = 0.f;
-  if (grp < groups)
-    for (int p = p_begin + grp; p < p_end; p += groups) v += g[(size_t)p * c + c0 + ch];
-  s[t] = v;
+  // eight accumulators (pixel step i into i % 8), so that the loads overlap;
+  // added in a fixed order
+  float v[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  if (grp < groups) {
+    int p = p_begin + grp;
+    for (; p + 7 * groups < p_end; p += 8 * groups) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] += g[(size_t)(p + u * groups) * c + c0 + ch];
+    }
+#pragma unroll
+    for (int u = 0; u < 7; ++u)
+      if (p + u * groups < p_end) v[u] += g[(size_t)(p + u * groups) * c + c0 + ch];
+  }
+  s[t] = ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
   __syncthreads();
   if (t < cc) {
     float tot = 0.f;
