@@ -84,7 +84,9 @@ struct WgradPlan {
 
 WgradPlan wgrad_plan(int batch, int H, int W, int cin, int cout, int ks) {
   WgradPlan p;
-  p.tm = cin > 32 ? 64 : (cin > 16 ? 32 : 16);
+  // input-channel tile: 64 unless a 32-wide tile divides cin and a 64-wide
+  // one would leave a partly empty last tile (96 = 3 x 32, not 2 x 64)
+  p.tm = cin > 32 ? (cin % 64 != 0 && cin % 32 == 0 ? 32 : 64) : (cin > 16 ? 32 : 16);
   p.nt = cout > 32 ? 64 : (cout > 16 ? 32 : 16);
   p.mtiles = (cin + p.tm - 1) / p.tm;
   p.ntiles = (cout + p.nt - 1) / p.nt;
