@@ -5,7 +5,9 @@
  * in Li, Ho, Wu & Zhang, "Lattice Boltzmann modelling of intrinsic
  * permeability": single-relaxation-time (BGK) lattice Boltzmann with the
  * normalised relaxation time tau (viscosity nu = (tau - 1/2)/3 in lattice
- * units, Eq. 1), the D2Q9 and D3Q19 lattices, pressure-driven flow along x
+ * units, Eq. 1; optionally two relaxation times, lbm_set_trt), with the full
+ * or the linear ("Stokes") equilibrium, the D2Q9 and D3Q19 lattices,
+ * pressure-driven flow along x
  * with density imposed at the inlet and outlet and symmetric side planes
  * (Fig. 1 and the first paragraph of the Results), iterated to steady Stokes
  * flow; the permeability follows from Darcy's law and the mass flow rate
@@ -20,7 +22,8 @@
  *                  (Guo, Zheng & Shi 2002); a ghost copies the solidity of the
  *                  edge node it extrapolates from.
  * With LBM_BC_PERIODIC the faces wrap instead, the flow is driven by the body
- * force, and rho_in = rho_out is the starting density.
+ * force (forcing of Guo, Zheng & Shi 2002), rho_in = rho_out is the starting
+ * density, and the permeability is Eq. 2: k = nu Q nx / (rho0 g nx ny nz).
  * Lengths are in lattice units; the permeability is in dx^2 with the pressure
  * gradient taken between the ghost planes: k = nu Q L / (A c_s^2 (rho_in -
  * rho_out)), L = nx + 1, A = ny * nz, c_s^2 = 1/3, and Q the mass flow rate,
