@@ -216,8 +216,8 @@ def main():
     ap.add_argument("--no-graph", action="store_true", help="batched workload: plain launches")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU runs are not "
-                                   "part of this build", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "this benchmark runs on one GPU; the multi-GPU slab "
+                                   "decomposition is not implemented", "n_gpus": args.gpus}))
         sys.exit(2)
 
     if args.workload == "c3_batch_fp32":
