@@ -394,3 +394,49 @@ def test_smooth_removes_trapped_oscillation():
         shifted.append((abs(s.permeability() - k0) / k0, one_step))
     assert shifted[0][0] > 1e-4 and shifted[0][1] > 1e-5, shifted   # the trap is real
     assert shifted[1][0] < 1e-6 and shifted[1][1] < 1e-8, shifted   # and removed
+
+
+@pytest.mark.parametrize("Q,shape", [
+    (9, (1, 2)), (9, (5, 65)), (9, (3, 130)),
+    (19, (1, 1, 2)), (19, (3, 9, 67)), (19, (70, 5, 5)),
+])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_linear_equilibrium_pressure_random_state(Q, shape, precision):
+    """The linear ("Stokes") equilibrium in the pressure-driven case (ghost
+    planes, mirrors, bounce-back) from a seeded random state, element by
+    element after one and five steps."""
+    rng = np.random.default_rng(hash(shape) % 1000 + 3)
+    mask = (rng.random(shape) < 0.25).astype(np.uint8)
+    if mask.ndim == 3 and Q == 9:
+        mask = mask[0]
+    if mask.all():
+        mask.reshape(-1)[0] = 0
+    s = lbm.Solver(mask, 0.7, 1.002, 0.998, precision=precision, lattice=Q)
+    s.set_linear_equilibrium(True)
+    o = oracle.Oracle(Q, mask, 0.7, 1.002, 0.998, linear_eq=True)
+    g0 = random_state(s, scale=1e-3, seed=2).cpu().numpy()
+    o.set_f(to_oracle_f(g0, Q))
+    for n in (1, 5):
+        s.step(n)
+        o.step(n)
+        g = state_view(s).cpu().numpy().astype(np.float64)
+        go = from_oracle_f(o.get_f(), Q, mask.reshape((1,) * (3 - mask.ndim) + mask.shape).shape)
+        fl = ~mask.reshape(go.shape[1:]).astype(bool)
+        err = np.abs(g[:, fl] - go[:, fl]).max()
+        scale = np.abs(go[:, fl]).max()
+        bound = 1e-10 * scale + field_floor(Q, o.steps) if precision == "fp64" else 1e-5 * scale
+        assert err <= bound, (n, err, bound)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_linear_equilibrium_pressure_qsgs(c1_mask, precision):
+    """C1 medium with the linear equilibrium: k and fields after 3000 steps."""
+    s = lbm.Solver(c1_mask, 0.8, 1.0005, 0.9995, precision=precision, lattice=9)
+    s.set_linear_equilibrium(True)
+    o = oracle.Oracle(9, c1_mask, 0.8, 1.0005, 0.9995, linear_eq=True)
+    s.step(3000)
+    o.step(3000)
+    kg, ko = s.permeability(), o.permeability()
+    assert abs(kg - ko) / ko <= TOL[precision], (kg, ko)
+    ok, rel = fields_match(s, o, TOL[precision])
+    assert ok, rel
