@@ -88,9 +88,12 @@ enum {
                              order; 1 one contiguous eighth per XCD (default); m >= 2 chunks
                              of m - 1 tile rows dealt round-robin */
   LBM_OPT_LINEAR_EQ = 2,  /* 1: equilibrium without the terms quadratic in u (Stokes); 0 (default) */
-  LBM_OPT_BAND = 6        /* > 0: banded tile order: bands of this many tile rows, one band
+  LBM_OPT_BAND = 6,       /* > 0: banded tile order: bands of this many tile rows, one band
                              per XCD at a time, each walked plane by plane (overrides
                              LBM_OPT_XCD_REMAP); default 16; 0: off */
+  LBM_OPT_WIDE_OFFSETS = 7 /* 1: address the populations with 64-bit offsets even when a
+                             direction group fits the 32-bit form (the form domains above
+                             4 GiB per group use; results are bitwise the same); 0 (default) */
 };
 
 typedef struct lbm_ctx lbm_ctx;               /* opaque; host metadata only */

@@ -66,6 +66,7 @@ struct lbm_ctx {
   uint64_t n_slots;    // slots in use per direction array (fluid nodes + padding)
   int band;            // 0 or tile rows per band (banded tile order)
   double trt_magic;    // > 0: TRT collision with this magic parameter; 0: BGK
+  int wide_offsets;    // 1: 64-bit population offsets even where 32-bit ones fit
 
   uint64_t* bits() const { return (uint64_t*)(work + L.off_bits); }
   uint32_t* pfx() const { return (uint32_t*)(work + L.off_pfx); }
@@ -93,7 +94,9 @@ namespace host {
 
 // Every direction group (at most 10 arrays of ps values) spans less than
 // 4 GiB: the step kernel can use 32-bit group-relative offsets.
-inline bool off32_ok(const lbm_ctx* c) { return 10ull * c->L.ps * c->L.esize < (1ull << 32); }
+inline bool off32_ok(const lbm_ctx* c) {
+  return !c->wide_offsets && 10ull * c->L.ps * c->L.esize < (1ull << 32);
+}
 
 // Divisor d >= 1 for FastDiv: l = ceil(log2 d), m = 2^32 (2^l - d) / d + 1.
 inline FastDiv make_fastdiv(uint32_t d) {

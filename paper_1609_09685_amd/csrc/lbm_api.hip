@@ -383,6 +383,7 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_geom* geom, const lbm_buffers* bufs
   c->n_slots = 0;
   c->band = 16;
   c->trt_magic = 0.0;
+  c->wide_offsets = 0;
 
   auto fail_free = [&](lbm_status st) { delete c; return st; };
   s = build_fluid_map(c);
@@ -531,6 +532,10 @@ lbm_status lbm_set_option(lbm_ctx* c, int32_t option, int64_t value) {
     case LBM_OPT_LINEAR_EQ:
       if (value != 0 && value != 1) return fail(LBM_EINVAL, "linear equilibrium is 0 or 1");
       c->linear_eq = (int)value;
+      return ok();
+    case LBM_OPT_WIDE_OFFSETS:
+      if (value != 0 && value != 1) return fail(LBM_EINVAL, "wide offsets is 0 or 1");
+      c->wide_offsets = (int)value;
       return ok();
     default:
       return fail(LBM_EINVAL, "unknown option %d", option);

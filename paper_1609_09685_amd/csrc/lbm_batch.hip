@@ -208,6 +208,8 @@ lbm_status upload_args(lbm_batch* b) {
       return fail(LBM_ESTATE, "sample %d: the linear-equilibrium option changed", d);
     if ((c->trt_magic > 0.0) != b->trt)
       return fail(LBM_ESTATE, "sample %d: the collision model changed", d);
+    if (off32_ok(c) != b->off32)
+      return fail(LBM_ESTATE, "sample %d: the offset width changed", d);
     const int p = c->parity;
     for (int j = 0; j < 2; ++j) {
       c->parity = p ^ j;

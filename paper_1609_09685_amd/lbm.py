@@ -114,6 +114,7 @@ def _check(status, allow=()):
 
 LBM_OPT_XCD_REMAP, LBM_OPT_LINEAR_EQ = 1, 2
 LBM_OPT_BAND = 6
+LBM_OPT_WIDE_OFFSETS = 7
 LBM_BATCH_OPT_GRAPH = 1
 
 
@@ -211,6 +212,11 @@ class Solver:
 
     def set_linear_equilibrium(self, on=True):
         self.set_option(LBM_OPT_LINEAR_EQ, 1 if on else 0)
+
+    def set_wide_offsets(self, on=True):
+        """Address the populations with 64-bit offsets (the form very large domains
+        use) even where 32-bit ones fit; results are bitwise the same."""
+        self.set_option(LBM_OPT_WIDE_OFFSETS, 1 if on else 0)
 
     def set_trt(self, magic=3.0 / 16.0):
         """Two-relaxation-time collision with the magic parameter
