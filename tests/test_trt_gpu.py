@@ -44,15 +44,15 @@ def _pair(Q, mask, precision, tau, magic, periodic=False, g=0.0, linear_eq=False
     (19, (1, 1, 2)), (19, (3, 9, 67)), (19, (2, 1, 129)), (19, (5, 3, 2)),
 ])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-@pytest.mark.parametrize("case", ["pressure", "periodic", "periodic_linear"])
+@pytest.mark.parametrize("case", ["pressure", "pressure_linear", "periodic", "periodic_linear"])
 def test_edge_shapes_random_state(Q, shape, precision, case):
     rng = np.random.default_rng(hash(shape) % 1000 + 11)
     mask = (rng.random(shape) < 0.25).astype(np.uint8)
     if mask.all():
         mask.reshape(-1)[0] = 0
-    periodic = case != "pressure"
+    periodic = case.startswith("periodic")
     s, o = _pair(Q, mask, precision, 0.7, MAGIC, periodic=periodic,
-                 g=2e-4 if periodic else 0.0, linear_eq=case == "periodic_linear")
+                 g=2e-4 if periodic else 0.0, linear_eq=case.endswith("linear"))
     g0 = random_state(s, scale=1e-3, seed=5).cpu().numpy()
     o.set_f(to_oracle_f(g0, Q))
     for n in (1, 5):
@@ -142,17 +142,20 @@ def test_bgk_special_case(precision):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_batch_trt_bitwise(precision):
+@pytest.mark.parametrize("periodic", [False, True])
+def test_batch_trt_bitwise(precision, periodic):
     """Samples with different magic parameters in one batch: bitwise equal to
-    the samples alone."""
+    the samples alone (pressure-driven and force-driven periodic)."""
     masks = [qsgs_2d(100, 50, p, j) for j, p in enumerate((0.7, 0.8, 0.75))]
     taus = (0.7, 0.9, 1.1)
     magics = (3 / 16, 1 / 4, 1 / 12)
+    kw = dict(boundary="periodic", body_force=1e-6) if periodic else {}
+    ri, ro = (1.0, 1.0) if periodic else (1.0005, 0.9995)
 
     def solvers():
         out = []
         for mk, t, mg in zip(masks, taus, magics):
-            s = lbm.Solver(mk, t, 1.0005, 0.9995, precision=precision, lattice=9)
+            s = lbm.Solver(mk, t, ri, ro, precision=precision, lattice=9, **kw)
             s.set_trt(mg)
             out.append(s)
         return out
