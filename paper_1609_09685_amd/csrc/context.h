@@ -41,7 +41,7 @@ struct Layout {
   uint64_t ps;           // slots per direction array: room for every segment's padding
   size_t f_bytes;
   int scan_blocks, seg_scan_blocks;
-  size_t off_bits, off_pfx, off_count, off_scan, off_seg, off_seg_scan, off_bplane, off_partial,
+  size_t off_bits, off_pfx, off_desc, off_count, off_scan, off_seg, off_seg_scan, off_bplane, off_partial,
       off_scalar, work_bytes;
   size_t bplane_one;     // elements of one parity of the boundary-plane array
   int partials;          // capacity of the partial array
@@ -70,6 +70,7 @@ struct lbm_ctx {
 
   uint64_t* bits() const { return (uint64_t*)(work + L.off_bits); }
   uint32_t* pfx() const { return (uint32_t*)(work + L.off_pfx); }
+  lbm::WordDesc* desc() const { return (lbm::WordDesc*)(work + L.off_desc); }
   uint32_t* count() const { return (uint32_t*)(work + L.off_count); }
   uint32_t* scan() const { return (uint32_t*)(work + L.off_scan); }
   uint32_t* seg() const { return (uint32_t*)(work + L.off_seg); }
@@ -124,8 +125,7 @@ StepArgs<T> step_args(const lbm_ctx* c) {
   a.src_g1 = a.src + (uint64_t)split * c->L.ps;
   a.dst_g1 = a.dst + (uint64_t)split * c->L.ps;
   a.ps_bytes = off32_ok(c) ? (uint32_t)(c->L.ps * sizeof(T)) : 0u;
-  a.bits = c->bits();
-  a.pfx = c->pfx();
+  a.desc = c->desc();
   a.bp_src = (const T*)c->bplane(c->parity);
   a.bp_dst = (T*)c->bplane(c->parity ^ 1);
   a.partial = c->partial();
@@ -135,6 +135,7 @@ StepArgs<T> step_args(const lbm_ctx* c) {
   a.nz = c->g.nz;
   a.nw = c->L.nw;
   a.seg = c->L.S;
+  a.seg_log = c->L.S == 4 ? 2 : (c->L.S == 2 ? 1 : 0);
   a.align = c->L.align;
   a.tiles_x = c->L.segs_per_row;
   const int rows = kRows / c->L.S;

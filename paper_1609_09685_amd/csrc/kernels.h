@@ -60,6 +60,7 @@
 #include <type_traits>
 
 #include "lattice.h"
+#include "pull_index.h"
 
 namespace lbm {
 
@@ -118,14 +119,14 @@ struct StepArgs {
   const T* src_g1;                 // src + group_split * ps (second direction group)
   T* dst_g1;
   uint32_t ps_bytes;               // ps * sizeof(T) (32-bit offset kernels)
-  const uint64_t* __restrict__ bits;   // fluid bitmap, guard-padded rows (FluidMap)
-  const uint32_t* __restrict__ pfx;
+  const WordDesc* __restrict__ desc;   // per-word records of the fluid bitmap [nz][ny][nw]
   const T* __restrict__ bp_src;    // edge-node moments of step t: [2 sides][D+1][nz*ny]
   T* __restrict__ bp_dst;          // edge-node moments written by this step
   double* __restrict__ partial;    // per-word flux partials (flux variant)
   uint64_t ps;                     // elements between two direction arrays
   int nx, ny, nz, nw;              // lattice; nw = bitmap words per row
   int seg;                         // S: words (64 x) per segment and tile: 1, 2 or 4
+  int seg_log;                     // log2(S)
   int tiles_x, tiles_y;            // ceil(nw / S), ceil(ny / (4 / S))
   uint32_t align;                  // slots per 128 bytes
   int blocks;                      // tiles_x * tiles_y * nz
@@ -310,66 +311,48 @@ __device__ __forceinline__ T ghost_term(const T* __restrict__ bp, int side, uint
   return wq * (drho_set - drb) * P;
 }
 
-// Bit `lane` of a wave-uniform 64-bit mask.
-__device__ __forceinline__ uint32_t lane_bit(uint64_t m, int lane) {
-  return (uint32_t)(m >> lane) & 1u;
+// The record of word w of row `row` (wave-uniform: a scalar load).
+template <class T>
+__device__ __forceinline__ WordDesc load_desc(const StepArgs<T>& a, uint32_t row, int w) {
+  return a.desc[row * (uint32_t)a.nw + (uint32_t)w];
 }
-
-// Bit `lane` of a wave-uniform 64-bit mask as 0 or ~0u: a 64-bit shift by the
-// lane id and a signed one-bit field extract.
-__device__ __forceinline__ uint32_t lane_mask(uint64_t m, int lane) {
-  return (uint32_t)__builtin_amdgcn_sbfe((int)(uint32_t)(m >> lane), 0u, 1u);
-}
-
-// (a & m) | (b & ~m): a where m is all ones, b where it is zero.
-__device__ __forceinline__ uint32_t pick(uint32_t m, uint32_t a, uint32_t b) {
-  return (a & m) | (b & ~m);
-}
-
-// pfx + popcount(m & ((1 << lane) - 1)): the compact index of the lane's node
-// when m is the fluid word of its row (two mbcnt instructions).
-__device__ __forceinline__ uint32_t lane_rank(uint64_t m, uint32_t pfx) {
-  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, pfx));
-}
-
-// The bitmap of one source row around the wave's word: words w-1, w, w+1, the
-// slot of the first fluid node of word w (base), the slot after the last fluid
-// node of word w-1 (end_lo) and the slot of the first fluid node of word w+1
-// (base_hi), all wave-uniform.  Slots run on within a segment, but a segment
-// boundary between two words leaves a padding gap, so the neighbours of lanes
-// 0 and 63 are numbered from their own words.
-struct RowWords {
-  uint64_t lo, mid, hi;
-  uint32_t base, end_lo, base_hi;
-  // periodic case, x-edge words only: fluid flag (0 / ~0u) and slot of the
-  // row's node nx - 1 (the source x - 1 of x = 0) and of its node 0
-  uint32_t last_fluid, last_slot, first_fluid, first_slot;
-};
 
 // Updates the node x = 64 w + lane of row (y, z); y, z, w are uniform across
-// the wave.  YZE: the row touches a symmetric plane (mirrors possible); XE: the
-// word holds x = 0 or x = nx - 1 (ghost planes possible).  Interior waves
-// (neither) skip all boundary logic.  OFF32: each direction group spans less
-// than 4 GiB, so loads and stores use a uniform group base plus a 32-bit lane
-// offset.  The post-collision populations go to out[i][lds_base + slot] (LDS;
-// lds_base = the block-local position of the segment minus its first slot).
-// Returns the node's x-momentum rho u_x (with a body force, j_x + F/2; 0 if
-// the node is not fluid).
+// the wave.  YZE: the row touches a symmetric plane (mirrors possible) or, with
+// periodic faces, a y / z face (wraps); XE: the word holds x = 0 or x = nx - 1.
+// Interior waves (neither) skip all boundary logic.  OFF32: each direction
+// group spans less than 4 GiB, so a load is a wave-uniform base plus a 32-bit
+// lane offset.  The post-collision populations go to out[i][lds_base + slot]
+// (LDS; lds_base = the block-local position of the segment minus its first
+// slot).  Returns the node's x-momentum (with a body force, j_x + F/2; 0 if the
+// node is not fluid).
+//
+// Gather.  Every source row is described by its word record (wave-uniform).
+// For direction i the lanes whose source is fluid form a 64-bit mask (the
+// row's bits, shifted by c_x), which selects per lane between the source slot
+// and the node's own slot of the opposite direction (bounce-back).  Both
+// candidates lie in one direction group; the load base is the group base plus
+// the smaller of the two direction offsets, so each candidate is one 32-bit
+// lane offset.
 template <class L, class T, bool LINEAR, bool OFF32, bool PER, bool TRT, bool YZE, bool XE>
 __device__ __forceinline__ T node_update(const StepArgs<T>& a, int y, int z, int w, int lane,
                                          T (*out)[kThreads], uint32_t lds_base) {
+  const WaveLane ln;
   const int x = (w << 6) + lane;
-  constexpr bool per = PER;   // faces wrap instead of mirror / ghost (periodic case)
+  constexpr bool per = PER;
   // symmetric planes (pressure case only)
   const bool y0 = YZE && !per && y == 0, y1 = YZE && !per && y == a.ny - 1;
   const bool z0 = YZE && !per && L::D == 3 && z == 0;
   const bool z1 = YZE && !per && L::D == 3 && z == a.nz - 1;
   const uint32_t row_self = (uint32_t)z * (uint32_t)a.ny + (uint32_t)y;
-  const uint32_t wi_self = row_self * (uint32_t)(a.nw + 2) + 1u + (uint32_t)w;
-  const uint32_t pi_self = row_self * (uint32_t)a.nw + (uint32_t)w;
+  WordEdges we;
+  we.x0 = XE && w == 0;
+  we.x1 = XE && w == ((a.nx - 1) >> 6);
+  we.e = (a.nx - 1) & 63;
 
-  // source rows (y + dy, z + dz), mirrored onto the own row at a symmetric plane
-  RowWords rw[3][3];
+  // source rows (y + dy, z + dz): mirrored onto the own row at a symmetric
+  // plane, wrapped to the opposite face in the periodic case
+  SourceRow rw[3][3];
   unroll<0, 3>([&](auto izc) {
     constexpr int dz = decltype(izc)::value - 1;
     if constexpr (L::D == 3 || dz == 0) {
@@ -377,7 +360,7 @@ __device__ __forceinline__ T node_update(const StepArgs<T>& a, int y, int z, int
         constexpr int dy = decltype(iyc)::value - 1;
         int ey = dy, ez = dz;
         if constexpr (YZE) {
-          if constexpr (PER) {   // wrap to the opposite face
+          if constexpr (PER) {
             if (dy < 0 && y == 0) ey = a.ny - 1;
             if (dy > 0 && y == a.ny - 1) ey = 1 - a.ny;
             if (dz < 0 && z == 0) ez = a.nz - 1;
@@ -387,136 +370,116 @@ __device__ __forceinline__ T node_update(const StepArgs<T>& a, int y, int z, int
             if ((dz < 0 && z0) || (dz > 0 && z1)) ez = 0;
           }
         }
-        const int drow = ez * a.ny + ey;
-        const uint64_t* wp = a.bits + (wi_self + (uint32_t)(drow * (a.nw + 2)));
-        const uint32_t* pp = a.pfx + (pi_self + (uint32_t)(drow * a.nw));
-        RowWords& r = rw[dz + 1][dy + 1];
-        r.lo = wp[-1];
-        r.mid = wp[0];
-        r.hi = wp[1];
-        r.base = pp[0];
-        // neighbour words' slots; at a row end the value is unused (ghost lanes)
-        r.end_lo = (w > 0 ? pp[-1] : pp[0]) + (uint32_t)__popcll(r.lo);
-        r.base_hi = w + 1 < a.nw ? pp[1] : pp[0];
-        if constexpr (XE && PER) {
-          {   // the nodes across the periodic x faces of this row
-            const uint64_t* row_w = wp - w;
-            const uint32_t* row_p = pp - w;
-            const int bl = (a.nx - 1) & 63;
-            const uint64_t wl = row_w[a.nw - 1];
-            r.last_fluid = (uint32_t)-(int)((wl >> bl) & 1ull);
-            r.last_slot = row_p[a.nw - 1] + (uint32_t)__popcll(wl & ((1ull << bl) - 1ull));
-            r.first_fluid = (uint32_t)-(int)(row_w[0] & 1ull);
-            r.first_slot = row_p[0];
-          }
-        }
+        const uint32_t row = row_self + (uint32_t)(ez * a.ny + ey);
+        const WordDesc d = load_desc(a, row, w);
+        SourceRow& r = rw[dz + 1][dy + 1];
+        r.mid = desc_bits(d);
+        r.base = d.base;
+        r.info = d.info;
+        if constexpr (XE && PER) row_x_faces(load_desc(a, row, 0), load_desc(a, row, a.nw - 1), a.nx, r);
       });
     }
   });
-  const RowWords& me = rw[1][1];
-  if (!lane_bit(me.mid, lane)) return T(0);   // solid node, or x >= nx
-  const uint32_t self = lane_rank(me.mid, me.base);
-  const bool x0 = XE && x == 0, x1 = XE && x == a.nx - 1;
-
-  // Gather: for every direction, whether the (mirrored) source is fluid and
-  // its compact index; a solid source reads the node's own slot of the
-  // opposite direction (halfway bounce-back).  Ghost sources (x-edge lanes)
-  // use the edge node b.  Both candidate addresses lie in the same direction
-  // group, so one load with a selected offset serves both.
+  const SourceRow& me = rw[1][1];
+  if (!ln.bit(me.mid)) return T(0);   // solid node, or x >= nx
+  const uint32_t self = ln.rank(me.mid, me.base);
   const uint32_t selfb = self * (uint32_t)sizeof(T);
+
   T g[L::Q];
-  uint32_t ghm[L::Q];   // ~0u: fluid ghost source (x-edge lanes), else 0
+  bool ghm[L::Q];   // pressure ghost source (x-edge lanes)
   unroll<0, L::Q>([&](auto qc) {
     constexpr int q = decltype(qc)::value;
     constexpr int cx = L::cx[q], cy = L::cy[q], cz = L::cz[q];
-    ghm[q] = 0u;
-    uint32_t sf = ~0u, si = self;   // ~0u: source fluid, 0: bounce-back
-    if constexpr (q != 0) {
-      const RowWords& r = rw[1 - cz][1 - cy];
-      const uint32_t r0 = lane_rank(r.mid, r.base);
-      if constexpr (cx == 0) {
-        sf = lane_mask(r.mid, lane);
-        si = r0;
-      } else if constexpr (cx > 0) {   // source x - 1: slot r0 - fluid(x - 1)
-        sf = lane_mask((r.mid << 1) | (r.lo >> 63), lane);
-        si = (lane == 0 ? r.end_lo : r0) + sf;
-        if constexpr (XE) {
-          if (x0) {
-            if constexpr (PER) { sf = r.last_fluid; si = r.last_slot; }
-            else { sf = lane_mask(r.mid, lane); si = r0; ghm[q] = sf; }
-          }
-        }
-      } else {                          // source x + 1: slot r0 + fluid(x)
-        const uint32_t f0 = lane_mask(r.mid, lane);
-        sf = lane_mask((r.mid >> 1) | (r.hi << 63), lane);
-        si = lane == 63 ? r.base_hi : r0 - f0;
-        if constexpr (XE) {
-          if (x1) {
-            if constexpr (PER) { sf = r.first_fluid; si = r.first_slot; }
-            else { sf = f0; si = r0; ghm[q] = sf; }
-          }
-        }
-      }
-    }
-    // direction read by a fluid source: q, or its mirror image
-    int k = q;
-    if constexpr (YZE && q != 0) {
-      bool fy = false, fz = false;
-      if constexpr (cy > 0) fy = y0;
-      if constexpr (cy < 0) fy = y1;
-      if constexpr (cz > 0) fz = z0;
-      if constexpr (cz < 0) fz = z1;
-      constexpr int kY = L::my[q], kZ = L::mz[q], kYZ = L::mz[L::my[q]];
-      k = fy ? (fz ? kYZ : kY) : (fz ? kZ : q);
-    }
-    constexpr int o = L::opp[q];
-    if constexpr (OFF32) {
-      constexpr int first = q < L::group_split ? 0 : L::group_split;
-      const char* base = q < L::group_split ? (const char*)a.src : (const char*)a.src_g1;
-      const uint32_t ck = (uint32_t)(k - first) * a.ps_bytes;
-      const uint32_t co = (uint32_t)(o - first) * a.ps_bytes;
-      const uint32_t off = pick(sf, si * (uint32_t)sizeof(T) + ck, selfb + co);
-      g[q] = *(const T*)(base + off);
+    ghm[q] = false;
+    if constexpr (q == 0) {
+      g[0] = a.src[self];
     } else {
-      const uint64_t idx = sf ? (uint64_t)k * a.ps + si : (uint64_t)o * a.ps + self;
-      g[q] = a.src[idx];
+      const SourceRow& r = rw[1 - cz][1 - cy];
+      // direction read by a fluid source: q, or its mirror image
+      int k = q;
+      if constexpr (YZE && q != 0) {
+        bool fy = false, fz = false;
+        if constexpr (cy > 0) fy = y0;
+        if constexpr (cy < 0) fy = y1;
+        if constexpr (cz > 0) fz = z0;
+        if constexpr (cz < 0) fz = z1;
+        constexpr int kY = L::my[q], kZ = L::mz[q], kYZ = L::mz[L::my[q]];
+        k = fy ? (fz ? kYZ : kY) : (fz ? kZ : q);
+      }
+      constexpr int o = L::opp[q];
+      uint64_t m, gm;
+      uint32_t off;
+      if constexpr (OFF32) {
+        // group base + the smaller of the two direction offsets, so that both
+        // candidates are non-negative 32-bit lane offsets
+        constexpr int first = q < L::group_split ? 0 : L::group_split;
+        const char* base = q < L::group_split ? (const char*)a.src : (const char*)a.src_g1;
+        uint32_t lo, dk, dob;   // lo + dk: direction read; lo + dob: opposite direction
+        if constexpr (!YZE) {   // k = q
+          if constexpr (o > q) {
+            lo = (uint32_t)(q - first) * a.ps_bytes;
+            dk = 0u;
+            dob = (uint32_t)(o - q) * a.ps_bytes;
+          } else {
+            lo = (uint32_t)(o - first) * a.ps_bytes;
+            dk = (uint32_t)(q - o) * a.ps_bytes;
+            dob = 0u;
+          }
+        } else {
+          const uint32_t ck = (uint32_t)(k - first) * a.ps_bytes;
+          const uint32_t co = (uint32_t)(o - first) * a.ps_bytes;
+          lo = ck < co ? ck : co;
+          dk = ck - lo;
+          dob = co - lo;
+        }
+        pull_offset<cx, PER, (uint32_t)sizeof(T)>(ln, r, ln.rank(r.mid, 0u), we, dk, m, off, gm);
+        const uint32_t ob = selfb + dob;
+        off = __builtin_unpredictable(ln.bit(m)) ? off : ob;
+        g[q] = *(const T*)(base + lo + off);
+      } else {
+        pull_offset<cx, PER, 1u>(ln, r, ln.rank(r.mid, 0u), we, 0u, m, off, gm);
+        const uint64_t idx = ln.bit(m) ? (uint64_t)k * a.ps + off : (uint64_t)o * a.ps + self;
+        g[q] = a.src[idx];
+      }
+      ghm[q] = ln.bit(gm);
     }
   });
 
   // Ghost populations: add the non-equilibrium extrapolation term.
   if constexpr (XE && !PER) {
-    if (x0 || x1) {
-      unroll<1, L::Q>([&](auto qc) {
-        constexpr int q = decltype(qc)::value;
-        constexpr int cx = L::cx[q], cy = L::cy[q], cz = L::cz[q];
-        if constexpr (cx != 0) {
-          if (ghm[q]) {
-            bool fy = false, fz = false;
-            if constexpr (cy > 0) fy = y0;
-            if constexpr (cy < 0) fy = y1;
-            if constexpr (cz > 0) fz = z0;
-            if constexpr (cz < 0) fz = z1;
-            const int ys = fy ? y : y - cy, zs = fz ? z : z - cz;
-            g[q] += ghost_term<L, LINEAR, T>(a.bp_src, cx > 0 ? 0 : 1, (uint32_t)a.nz * a.ny,
-                                             (uint32_t)zs * a.ny + ys,
-                                             cx > 0 ? a.drho_in : a.drho_out, T(L::w[q]), cx,
-                                             fy ? -cy : cy, fz ? -cz : cz);
-          }
+    unroll<1, L::Q>([&](auto qc) {
+      constexpr int q = decltype(qc)::value;
+      constexpr int cx = L::cx[q], cy = L::cy[q], cz = L::cz[q];
+      if constexpr (cx != 0) {
+        if (ghm[q]) {
+          bool fy = false, fz = false;
+          if constexpr (cy > 0) fy = y0;
+          if constexpr (cy < 0) fy = y1;
+          if constexpr (cz > 0) fz = z0;
+          if constexpr (cz < 0) fz = z1;
+          const int ys = fy ? y : y - cy, zs = fz ? z : z - cz;
+          g[q] += ghost_term<L, LINEAR, T>(a.bp_src, cx > 0 ? 0 : 1, (uint32_t)a.nz * a.ny,
+                                           (uint32_t)zs * a.ny + ys,
+                                           cx > 0 ? a.drho_in : a.drho_out, T(L::w[q]), cx,
+                                           fy ? -cy : cy, fz ? -cz : cz);
         }
-      });
-    }
+      }
+    });
   }
 
-  T drho = T(0), jx = T(0), jy = T(0), jz = T(0);
-  unroll<0, L::Q>([&](auto qc) {
-    constexpr int q = decltype(qc)::value;
-    drho += g[q];
-    if constexpr (L::cx[q] == 1) jx += g[q];
-    if constexpr (L::cx[q] == -1) jx -= g[q];
-    if constexpr (L::cy[q] == 1) jy += g[q];
-    if constexpr (L::cy[q] == -1) jy -= g[q];
-    if constexpr (L::cz[q] == 1) jz += g[q];
-    if constexpr (L::cz[q] == -1) jz -= g[q];
+  // Moments from the sums and differences of opposite pairs (q, q + 1).
+  T drho = g[0], jx = T(0), jy = T(0), jz = T(0);
+  unroll<0, (L::Q - 1) / 2>([&](auto pc) {
+    constexpr int q = 1 + 2 * decltype(pc)::value, o = q + 1;
+    static_assert(L::opp[q] == o && L::w[q] == L::w[o], "opposite pairs (q, q + 1)");
+    drho += g[q] + g[o];
+    const T d = g[q] - g[o];
+    if constexpr (L::cx[q] == 1) jx += d;
+    if constexpr (L::cx[q] == -1) jx -= d;
+    if constexpr (L::cy[q] == 1) jy += d;
+    if constexpr (L::cy[q] == -1) jy -= d;
+    if constexpr (L::cz[q] == 1) jz += d;
+    if constexpr (L::cz[q] == -1) jz -= d;
   });
   // with a body force (Guo et al. 2002) the velocity carries half the step's
   // force density: rho u = j + F/2
@@ -572,27 +535,45 @@ __device__ __forceinline__ T node_update(const StepArgs<T>& a, int y, int z, int
       g[q] = v;
     });
   } else if constexpr (!PER) {
-    // BGK, g' = (1 - omega) g + omega g_eq.  A direction and its opposite
-    // share the even part of the equilibrium, A = drho + rho (9/2 (c.u)^2 -
-    // 3/2 u.u), and differ in the sign of the odd part, B = 3 rho (c.u):
-    // g_eq = w (A + B) and w (A - B).
-    const T om = a.omega, om1 = T(1) - a.omega, rho3 = T(3) * rho;
-    {
-      T A0 = drho;
-      if constexpr (!LINEAR) A0 = drho - rho * usq15;
-      g[0] = om1 * g[0] + (om * T(L::w[0])) * A0;
-      out[0][lds_base + self] = g[0];
-    }
+    // BGK, g' = (1 - omega) g + omega g_eq.  With a = omega w_i, the relaxed
+    // equilibrium is a [drho + rho (3 c.u + 9/2 (c.u)^2 - 3/2 u.u)]
+    // = c0 + c1 (c.u)^2 +- c2 (c.u) for a direction and its opposite, where
+    // c0 = a (drho - rho 3/2 u.u), c1 = 9/2 a rho, c2 = 3 a rho depend only on
+    // the weight class (the linear equilibrium: c0 = a drho, c1 = 0, c2 = 3 a).
+    const T om = a.omega, om1 = T(1) - a.omega;
+    T ev = drho;
+    if constexpr (!LINEAR) ev = drho - rho * usq15;
+    g[0] = om1 * g[0] + (om * T(L::w[0])) * ev;
+    out[0][lds_base + self] = g[0];
+    T c0[2], c1[2], c2[2];   // [0] axis directions, [1] diagonal ones
+    unroll<0, 2>([&](auto cc) {
+      constexpr int c = decltype(cc)::value;
+      const T ac = om * T(L::w[c == 0 ? 1 : L::Q - 1]);
+      c0[c] = ac * ev;
+      if constexpr (LINEAR) {
+        c1[c] = T(0);
+        c2[c] = T(3) * ac;
+      } else {
+        const T ra = ac * rho;
+        c1[c] = T(4.5) * ra;
+        c2[c] = T(3) * ra;
+      }
+    });
     unroll<0, (L::Q - 1) / 2>([&](auto pc) {
       constexpr int q = 1 + 2 * decltype(pc)::value, o = q + 1;
-      static_assert(L::opp[q] == o && L::w[q] == L::w[o], "opposite pairs (q, q + 1)");
+      constexpr int c = L::w[q] == L::w[1] ? 0 : 1;
+      static_assert(L::w[q] == L::w[c == 0 ? 1 : L::Q - 1], "two weight classes");
       const T cu = dot_c<L, q>(ux, uy, uz);
-      T A = drho;
-      if constexpr (!LINEAR) A = drho + rho * (T(4.5) * (cu * cu) - usq15);
-      const T ow = om * T(L::w[q]);
-      const T wA = ow * A, wB = ow * (rho3 * cu);
-      g[q] = om1 * g[q] + (wA + wB);
-      g[o] = om1 * g[o] + (wA - wB);
+      T P, M;
+      if constexpr (LINEAR) {
+        P = c2[c] * cu + c0[c];
+        M = c0[c] - c2[c] * cu;
+      } else {
+        P = (c1[c] * cu + c2[c]) * cu + c0[c];
+        M = (c1[c] * cu - c2[c]) * cu + c0[c];
+      }
+      g[q] = om1 * g[q] + P;
+      g[o] = om1 * g[o] + M;
       out[q][lds_base + self] = g[q];
       out[o][lds_base + self] = g[o];
     });
@@ -617,6 +598,7 @@ __device__ __forceinline__ T node_update(const StepArgs<T>& a, int y, int z, int
   }
 
   if constexpr (XE && !PER) {
+    const bool x0 = we.x0 && x == 0, x1 = we.x1 && x == a.nx - 1;
     if (x0 || x1) {
       // edge-node moments of the stored state, read by the next step's ghosts
       T bd, bx, by, bz;
@@ -710,22 +692,20 @@ __device__ __forceinline__ void step_tile(const StepArgs<T>& a, const uint32_t h
   }
   const int S = a.seg;
   const int wave = threadIdx.y, lane = threadIdx.x;
-  const int j = uniform(wave / S);                  // row of the tile
+  const int j = uniform(wave >> a.seg_log);         // row of the tile
   const int y = uniform(ty * (kRows / S) + j);
   const int w0 = tx * S;                            // first word of the segment
-  const int w = uniform(w0 + wave % S);
+  const int w = uniform(w0 + (wave & (S - 1)));
   z = uniform(z);
   const bool row_ok = y < a.ny;
   const uint32_t row = (uint32_t)z * (uint32_t)a.ny + (uint32_t)y;
-  // segment of this wave's row: first slot and number of fluid nodes
+  // segment of this wave's row: first slot and number of fluid nodes (slots
+  // run on without gaps inside a segment)
   uint32_t first = 0u, count = 0u;
   if (row_ok) {
-    first = a.pfx[row * (uint32_t)a.nw + (uint32_t)w0];
-    const uint64_t* wd = a.bits + row * (uint32_t)(a.nw + 2) + 1u;
-    const int we = min(w0 + S, a.nw);
-    for (int i = w0; i < we; ++i) count += (uint32_t)__popcll(wd[i]);
+    segment_extent(load_desc(a, row, w0), load_desc(a, row, min(w0 + S, a.nw) - 1), first, count);
   }
-  if (wave % S == 0 && lane == 0) {
+  if ((wave & (S - 1)) == 0 && lane == 0) {
     seg_first[j] = first;
     seg_count[j] = count;
   }
@@ -741,24 +721,28 @@ __device__ __forceinline__ void step_tile(const StepArgs<T>& a, const uint32_t h
     }
   }
   __syncthreads();
-  // whole-line stores: thread t writes position t of its row's segment; the
+  // whole-line stores: thread t writes position t of its row's segment (zero
+  // past the segment's fluid nodes, up to the next 128-byte boundary); the
   // next step reads them from HBM anyway, so they bypass the caches
-  // (nontemporal), which pays now that no store leaves a partial line
+  // (nontemporal)
   const int t = wave * kWave + lane;
-  const int jj = t / (S * kWave);
-  const uint32_t r = (uint32_t)(t - jj * S * kWave);
+  const int sh = a.seg_log + 6;                     // log2(S * 64)
+  const int jj = t >> sh;
+  const uint32_t r = (uint32_t)t & ((1u << sh) - 1u);
   const uint32_t n = seg_count[jj];
   const uint32_t lim = (n + a.align - 1u) & ~(a.align - 1u);
   if (r < lim) {
     const uint32_t slot = seg_first[jj] + r;
+    const bool live = r < n;
     unroll<0, L::Q>([&](auto qc) {
       constexpr int q = decltype(qc)::value;
-      const T v = r < n ? out[q][t] : T(0);
+      T v = out[q][t];
+      v = live ? v : T(0);
       if constexpr (OFF32) {
         constexpr int f = q < L::group_split ? 0 : L::group_split;
-        char* base = q < L::group_split ? (char*)a.dst : (char*)a.dst_g1;
-        __builtin_nontemporal_store(
-            v, (T*)(base + (slot * (uint32_t)sizeof(T) + (uint32_t)(q - f) * a.ps_bytes)));
+        char* base = (q < L::group_split ? (char*)a.dst : (char*)a.dst_g1) +
+                     (uint32_t)(q - f) * a.ps_bytes;
+        __builtin_nontemporal_store(v, (T*)(base + slot * (uint32_t)sizeof(T)));
       } else {
         __builtin_nontemporal_store(v, a.dst + ((uint64_t)q * a.ps + slot));
       }
@@ -909,6 +893,21 @@ static __global__ __launch_bounds__(256) void k_word_pfx(const uint32_t* __restr
   pfx[i] = p;
 }
 
+// Per-word records of the step kernel (WordDesc) from the bitmap (guard words
+// of zeros at both row ends) and the slots of the words.
+static __global__ __launch_bounds__(256) void k_word_desc(FluidMap fm, WordDesc* __restrict__ desc,
+                                                   uint64_t nwords) {
+  const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= nwords) return;
+  const uint64_t row = i / fm.nw;
+  const int w = (int)(i % fm.nw);
+  const uint64_t* wr = fm.bits + row * (uint64_t)(fm.nw + 2) + 1;
+  const uint32_t* pr = fm.pfx + row * (uint64_t)fm.nw;
+  const bool has_prev = w > 0, has_next = w + 1 < fm.nw;
+  desc[i] = make_word_desc(wr[w - 1], wr[w], wr[w + 1], has_prev ? pr[w - 1] : 0u, pr[w],
+                           has_next ? pr[w + 1] : 0u, has_prev, has_next);
+}
+
 // Slot of every node (x fastest), -1 for solids.
 static __global__ __launch_bounds__(256) void k_slot_map(FluidMap fm, int32_t* __restrict__ map) {
   const uint64_t m = (uint64_t)blockIdx.x * 256 + threadIdx.x;
@@ -943,8 +942,9 @@ __global__ __launch_bounds__(256) void k_init_rest(T* __restrict__ f, T* __restr
   });
 }
 
-// Equilibrium of given fields: rho [nz][ny][nx], u [D][nz][ny][nx] (float32).
-template <class L, class T>
+// Equilibrium of given fields: rho [nz][ny][nx], u [D][nz][ny][nx] (float32);
+// the model's own equilibrium (LINEAR: without the terms quadratic in u).
+template <class L, class T, bool LINEAR>
 __global__ __launch_bounds__(256) void k_init_fields(T* __restrict__ f, FluidMap fm,
                                                      const float* __restrict__ rho_f,
                                                      const float* __restrict__ u_f, uint64_t ps,
@@ -964,7 +964,7 @@ __global__ __launch_bounds__(256) void k_init_fields(T* __restrict__ f, FluidMap
   const double drho = rho - rho0;
   unroll<0, L::Q>([&](auto qc) {
     constexpr int q = decltype(qc)::value;
-    f[(uint64_t)q * ps + k] = (T)geq<L, q, false, double>(drho, rho, ux, uy, uz, usq15);
+    f[(uint64_t)q * ps + k] = (T)geq<L, q, LINEAR, double>(drho, rho, ux, uy, uz, usq15);
   });
 }
 

@@ -5,6 +5,7 @@
 // Device memory is the caller's; the work buffer is carved here into
 //   bits     uint64 [nz][ny][nw + 2]     fluid bitmap with guard words
 //   pfx      uint32 [nz][ny][nw]         compact index of each word's first fluid node
+//   desc     WordDesc [nz][ny][nw]       per-word records read by the step kernel
 //   count    uint32 [nz][ny][nw]         fluid nodes per word (set-up only)
 //   scan     uint32 [scan blocks]        block totals of the prefix scan (set-up only)
 //   bplane   T [2 parities][2 sides][D+1][nz][ny]   edge-node moments
@@ -112,6 +113,8 @@ lbm_status make_layout(const lbm_geom* g, Layout* L) {
   off = align_up(off + L->rows * (L->nw + 2) * 8, 256);
   L->off_pfx = off;
   off = align_up(off + nwords * 4, 256);
+  L->off_desc = off;
+  off = align_up(off + nwords * sizeof(WordDesc), 256);
   L->off_count = off;
   off = align_up(off + nwords * 4, 256);
   L->off_scan = off;
@@ -165,9 +168,9 @@ lbm_status launch_reset(lbm_ctx* c, int mode) {
 
 template <class Lat, class T>
 lbm_status launch_fields(lbm_ctx* c, const float* rho, const float* u) {
-  k_init_fields<Lat, T><<<grid_1d(n_nodes(c)), 256, 0, c->stream>>>(
-      (T*)c->f[c->parity], c->fmap(), rho, u, c->L.ps, c->g.rho0,
-      0.5 * (double)force_density<T>(c));
+  auto kern = c->linear_eq ? k_init_fields<Lat, T, true> : k_init_fields<Lat, T, false>;
+  kern<<<grid_1d(n_nodes(c)), 256, 0, c->stream>>>((T*)c->f[c->parity], c->fmap(), rho, u, c->L.ps,
+                                                   c->g.rho0, 0.5 * (double)force_density<T>(c));
   HIP_TRY(hipGetLastError());
   return launch_bplane<Lat, T>(c);
 }
@@ -278,6 +281,8 @@ lbm_status build_fluid_map(lbm_ctx* c) {
   if (s != LBM_OK) return s;
   k_word_pfx<<<grid_1d(nwords), 256, 0, c->stream>>>(c->count(), c->seg(), c->pfx(), nwords, L.nw,
                                                       L.S, L.segs_per_row);
+  HIP_TRY(hipGetLastError());
+  k_word_desc<<<grid_1d(nwords), 256, 0, c->stream>>>(c->fmap(), c->desc(), nwords);
   HIP_TRY(hipGetLastError());
   uint64_t h[2] = {0, 0};
   HIP_TRY(hipMemcpyAsync(h, totals, sizeof h, hipMemcpyDeviceToHost, c->stream));

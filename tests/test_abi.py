@@ -27,11 +27,16 @@ def _nm_exports(path):
     return {ln.split()[-1] for ln in out.splitlines() if ln.strip()}
 
 
+def _library_of(header):
+    from paper_1609_09685_amd import build
+    return build.PROBE_LIB if os.path.basename(header) == "lbm_probe.h" else lbm.library_path()
+
+
 @pytest.mark.parametrize("header", sorted(glob.glob(os.path.join(ROOT, "include", "*.h"))))
 def test_every_declared_symbol_is_exported(header):
     names = declared(header)
     assert names
-    path = lbm.library_path()
+    path = _library_of(header)
     exported = _nm_exports(path)
     missing = [n for n in names if n not in exported]
     assert not missing, f"{os.path.basename(header)}: not exported: {missing}"
@@ -221,3 +226,20 @@ def test_wsn_sizes_and_validation():
     assert L.wsn_adam(fake, fake, fake, fake, 10, 1e-3, 0.9, 0.999, 1e-8, 0, None) == lbm.LBM_EINVAL
     assert L.wsn_adam(fake, fake, fake, fake, 10, 1e-3, 1.0, 0.999, 1e-8, 1, None) == lbm.LBM_EINVAL
     assert L.wsn_mse_work(0, ctypes.byref(n)) == lbm.LBM_EINVAL
+
+
+def test_probe_rejects_bad_arguments():
+    """The streaming probes validate before launching (no GPU needed)."""
+    from paper_1609_09685_amd import build
+    lib = ctypes.CDLL(build.PROBE_LIB)
+    f = lib.lbm_probe_stream
+    f.restype = ctypes.c_int
+    f.argtypes = [ctypes.c_int] * 4 + [ctypes.c_uint64] + [ctypes.c_void_p] * 4
+    p = ctypes.c_void_p(256)
+    assert f(3, 1, 1, 19, 1024, p, p, p, None) == -1      # mode
+    assert f(0, 2, 1, 19, 1024, p, p, p, None) == -1      # vector width
+    assert f(0, 1, 1, 7, 1024, p, p, p, None) == -1       # array count
+    assert f(0, 4, 1, 19, 1000, p, p, p, None) == -1      # n not a multiple of 1024
+    assert f(0, 1, 1, 19, 0, p, p, p, None) == -1         # empty
+    assert f(1, 1, 0, 19, 1024, p, None, None, None) == -1  # read mode without a sink
+    assert f(0, 1, 1, 19, 1024, ctypes.c_void_p(258), p, p, None) == -1   # misaligned
