@@ -73,8 +73,8 @@ def kernel_source_hash():
     """Short hash of the step kernel's sources, to tie profiled counters to them."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("kernels.h", "lattice.h", "context.h", "step_launch.h", "step_launch.hip",
-              "lbm_api.hip"):
+    for f in ("kernels.h", "pull_index.h", "lattice.h", "context.h", "step_launch.h",
+              "step_launch.hip", "lbm_api.hip"):
         with open(os.path.join(ROOT, "paper_1609_09685_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -98,28 +98,49 @@ def profiled_traffic(workload):
     return int(fields["traffic_bytes_per_launch"])
 
 
-def copy_ceiling(gib=4, reps=5):
-    """A plain device-to-device copy of `gib` GiB (torch's copy kernel), timed
-    with HIP events: the achievable streaming bandwidth on this GPU, and the
-    reference kernel of known size for scaling the HBM byte counters."""
+def stream_ceilings(n_per_array=80_530_432, arrays=19, reps=5):
+    """What plain streaming of the step's kind of data reaches on this GPU: the
+    hand-written kernels of liblbmprobe.so (include/lbm_probe.h) over `arrays`
+    arrays of n floats (the 512^3 workload's fluid populations), timed with HIP
+    events on torch's current stream.  GB/s counts the bytes each pass moves."""
+    import ctypes
     import torch
-    n = gib * (1 << 30) // 4
-    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    from paper_1609_09685_amd import build as _b
+    lib = ctypes.CDLL(_b.PROBE_LIB)
+    lib.lbm_probe_stream.restype = ctypes.c_int
+    lib.lbm_probe_stream.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                     ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.c_void_p, ctypes.c_void_p]
+    n = n_per_array // 1024 * 1024
+    src = torch.zeros(arrays * n, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
-    dst.copy_(src)
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        dst.copy_(src)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
-    moved = 2 * n * 4
+    sink = torch.zeros(4, dtype=torch.float32, device="cuda")
+    st = torch.cuda.current_stream()
+    out = {"arrays": arrays, "floats_per_array": n}
+    for name, mode, vec, nt in (("copy_dword_nt", 0, 1, 1), ("copy_dwordx4_nt", 0, 4, 1),
+                                ("copy_dword", 0, 1, 0), ("read_dword", 1, 1, 0),
+                                ("read_dwordx4", 1, 4, 0), ("write_dword_nt", 2, 1, 1),
+                                ("write_dwordx4_nt", 2, 4, 1)):
+        def run():
+            rc = lib.lbm_probe_stream(mode, vec, nt, arrays, n, src.data_ptr(), dst.data_ptr(),
+                                      sink.data_ptr(), ctypes.c_void_p(st.cuda_stream))
+            if rc != 0:
+                raise RuntimeError(f"lbm_probe_stream failed ({rc})")
+        run()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            run()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        moved = arrays * n * 4 * (2 if mode == 0 else 1)
+        out[name] = round(moved / (ms / 1e3) / 1e9, 1)
     del src, dst
     torch.cuda.empty_cache()
-    return {"bytes_per_copy": moved, "ms": round(ms, 4), "gbs": round(moved / (ms / 1e3) / 1e9, 1)}
+    return out
 
 
 C3_SIZES = [(400, 200), (800, 400), (1200, 600)]
@@ -248,8 +269,9 @@ def main():
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
     ms_step = ms / args.steps
+    log(f"timed {args.steps} steps: {ms_step:.4f} ms/step")
     k = s.permeability()
-    log(f"timed {args.steps} steps: {ms_step:.4f} ms/step, k after {s.steps} steps = {k:.6e}")
+    log(f"k after {s.steps} steps = {k:.6e}")
     mlups = N * args.steps / (ms / 1e3) / 1e6
     alg_bytes = n_fluid * 2 * Q * esize + N * 1
     achieved = alg_bytes / (ms_step / 1e3) / 1e9
@@ -277,8 +299,8 @@ def main():
                      if (args.band, args.xcd_remap) == (16, 1) else None,
                      "kernel": "k_step", "algorithmic_bytes_per_launch": alg_bytes},
     }
-    out["copy_ceiling"] = copy_ceiling()
-    log(f"plain copy: {out['copy_ceiling']['gbs']:.0f} GB/s")
+    out["stream_ceilings"] = stream_ceilings(arrays=Q)
+    log(f"stream ceilings (GB/s): {out['stream_ceilings']}")
     if not args.no_cpu_baseline:
         log("cpu baseline ...")
         out["cpu_baseline"] = cpu_baseline(Q, mask, tau, rin, rout)

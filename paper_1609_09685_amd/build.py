@@ -3,6 +3,8 @@
 * ``libqsgs.so``  - host C++ (OpenMP) mask generator, built with g++.
 * ``liblbm.so``   - the HIP solver library for gfx950 behind the C ABI in
   ``include/lbm.h``, built with hipcc.
+* ``liblbmprobe.so`` - streaming-ceiling kernels for the benchmark
+  (``include/lbm_probe.h``), built with hipcc.
 
 Run ``python -m paper_1609_09685_amd.build`` (or ``__graft_entry__.build()``).
 """
@@ -16,6 +18,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 QSGS_LIB = os.path.join(PKG, "libqsgs.so")
 LBM_LIB = os.path.join(PKG, "liblbm.so")
+PROBE_LIB = os.path.join(PKG, "liblbmprobe.so")
 ARCH = "gfx950"
 
 # Sources of liblbm.so, each compiled to an object of its own.
@@ -72,9 +75,17 @@ def build_lbm(verbose=False):
     return LBM_LIB
 
 
+def build_probe(verbose=False):
+    _run(["hipcc", *HIPCC_FLAGS, f"-I{INCLUDE}", "-o", PROBE_LIB + ".tmp",
+          os.path.join(CSRC, "probe.hip")], verbose)
+    os.replace(PROBE_LIB + ".tmp", PROBE_LIB)
+    return PROBE_LIB
+
+
 def build_all(verbose=False):
     build_qsgs(verbose)
     build_lbm(verbose)
+    build_probe(verbose)
 
 
 if __name__ == "__main__":
