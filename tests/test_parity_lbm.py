@@ -177,9 +177,15 @@ def test_checkpoint_restore_bitwise(c1_mask):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_linear_start_and_set_macro(c1_mask, precision):
+@pytest.mark.parametrize("linear_eq", [False, True])
+def test_linear_start_and_set_macro(c1_mask, precision, linear_eq):
+    """Linear-density start, then a start from fields (the equilibrium of the
+    oracle's fields, in the model's own equilibrium: full or linear)."""
     import torch
     s, o = _pair(9, c1_mask, precision, **C1, start="linear")
+    if linear_eq:
+        s.set_linear_equilibrium(True)
+        o = oracle.Oracle(9, c1_mask, **C1, start="linear", linear_eq=True)
     s.step(700)
     o.step(700)
     assert abs(s.permeability() - o.permeability()) / abs(o.permeability()) <= TOL[precision]
@@ -188,7 +194,7 @@ def test_linear_start_and_set_macro(c1_mask, precision):
     rho_f = np.nan_to_num(rho, nan=1.0).astype(np.float32)
     u_f = np.nan_to_num(np.moveaxis(u[..., :2], -1, 0), nan=0.0).astype(np.float32)
     s.set_macro(torch.from_numpy(rho_f), torch.from_numpy(u_f))
-    o2 = oracle.Oracle(9, c1_mask, **C1)
+    o2 = oracle.Oracle(9, c1_mask, **C1, linear_eq=linear_eq)
     o2.init_fields(rho_f.astype(np.float64), np.moveaxis(u_f, 0, -1).astype(np.float64))
     s.step(300)
     o2.step(300)
