@@ -161,6 +161,18 @@ lbm_status lbm_step(lbm_ctx *ctx, int64_t n);
 /* Mass flow rate Q of the current state (FP64 reduction, deterministic). */
 lbm_status lbm_flux(lbm_ctx *ctx, double *q_out);
 
+/* lbm_flux for callers that cannot allocate device memory or that must not
+ * touch the context's work buffer (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): the same kernels and the
+ * same result, bitwise, but the flux pass's partials, their chunk sums and the
+ * result live in a scratch array of the library (one per GPU, 2 MiB plus a
+ * few chunk sums, allocated with the library's code object and held until the
+ * process ends).  Allocates nothing.  Limit: at most 2^26 population slots
+ * (lbm_query_sizes' f_bytes / (Q * element size)), LBM_EINVAL beyond.  Every
+ * call on one GPU uses that GPU's one scratch array: calls that overlap on one
+ * GPU (other threads, other streams) race and may return each other's flux. */
+lbm_status lbm_flux_noalloc(lbm_ctx *ctx, double *q_out);
+
 /* Darcy permeability of the current state in lattice units (dx^2).
  * LBM_ENOFLOW (k_out = 0) if the flux is exactly zero. */
 lbm_status lbm_permeability(lbm_ctx *ctx, double *k_out);

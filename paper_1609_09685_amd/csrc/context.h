@@ -169,6 +169,8 @@ StepArgs<T> step_args(const lbm_ctx* c) {
 
 
 inline unsigned grid_1d(uint64_t n) { return (unsigned)((n + 255) / 256); }
+// Partials of the flux pass over the slots of c (one per block of 256 slots).
+inline unsigned flux_partials(const lbm_ctx* c) { return grid_1d(c->n_slots ? c->n_slots : 1); }
 inline uint64_t n_nodes(const lbm_ctx* c) { return (uint64_t)c->g.nx * c->g.ny * c->g.nz; }
 
 

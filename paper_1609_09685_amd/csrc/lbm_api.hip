@@ -17,6 +17,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 
 #include "context.h"
@@ -176,10 +177,10 @@ lbm_status launch_fields(lbm_ctx* c, const float* rho, const float* u) {
 }
 
 template <class Lat, class T>
-lbm_status launch_flux(lbm_ctx* c, int* nparts) {
-  const unsigned nb = grid_1d(c->n_slots ? c->n_slots : 1);
+lbm_status launch_flux(lbm_ctx* c, double* partial, int* nparts) {
+  const unsigned nb = flux_partials(c);
   k_flux<Lat, T><<<nb, 256, 0, c->stream>>>((const T*)c->f[c->parity], c->n_slots, c->L.ps,
-                                              c->partial());
+                                              partial);
   HIP_TRY(hipGetLastError());
   *nparts = (int)nb;
   return LBM_OK;
@@ -222,7 +223,7 @@ template <class Lat, class T> struct Fields {
   }
 };
 template <class Lat, class T> struct Flux {
-  static lbm_status run(lbm_ctx* c, int* np) { return launch_flux<Lat, T>(c, np); }
+  static lbm_status run(lbm_ctx* c, double* p, int* np) { return launch_flux<Lat, T>(c, p, np); }
 };
 template <class Lat, class T> struct Macro {
   static lbm_status run(lbm_ctx* c, void* r, void* u, int d) { return launch_macro<Lat, T>(c, r, u, d); }
@@ -302,21 +303,27 @@ lbm_status build_fluid_map(lbm_ctx* c) {
 namespace lbm {
 namespace host {
 
-lbm_status flux_pass(lbm_ctx* c, int* nparts) { return dispatch<Flux>(c, nparts); }
+lbm_status flux_pass(lbm_ctx* c, int* nparts) { return dispatch<Flux>(c, c->partial(), nparts); }
 
-// Reduces n partials of the last flux pass into scalar[0] and reads it back.
-lbm_status reduce_flux(lbm_ctx* c, int n, double* q) {
+// Reduces n partials at `partial` (chunk sums to `chunk`, the result to *dev)
+// and reads the result back.
+lbm_status reduce_partials(lbm_ctx* c, const double* partial, double* chunk, double* dev, int n,
+                           double* q) {
   const int nch = (n + kChunk - 1) / kChunk;
-  double* chunk = c->partial() + c->L.partials;
-  k_reduce_chunks<<<nch, 1024, 0, c->stream>>>(c->partial(), n, chunk);
+  k_reduce_chunks<<<nch, 1024, 0, c->stream>>>(partial, n, chunk);
   HIP_TRY(hipGetLastError());
-  k_reduce_final<<<1, 1024, 0, c->stream>>>(chunk, nch, 1.0 / c->g.nx, c->scalar());
+  k_reduce_final<<<1, 1024, 0, c->stream>>>(chunk, nch, 1.0 / c->g.nx, dev);
   HIP_TRY(hipGetLastError());
   double h = 0.0;
-  HIP_TRY(hipMemcpyAsync(&h, c->scalar(), sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipMemcpyAsync(&h, dev, sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
   *q = h;
   return LBM_OK;
+}
+
+// Reduces n partials of the last flux pass into scalar[0] and reads it back.
+lbm_status reduce_flux(lbm_ctx* c, int n, double* q) {
+  return reduce_partials(c, c->partial(), c->partial() + c->L.partials, c->scalar(), n, q);
 }
 
 lbm_status current_flux(lbm_ctx* c, double* q) {
@@ -338,6 +345,45 @@ double perm_from_flux(const lbm_ctx* c, double q) {
 
 }  // namespace host
 }  // namespace lbm
+
+namespace {
+
+using namespace lbm::host;
+
+// Scratch of lbm_flux_noalloc: the flux pass's per-block partials, their chunk
+// sums and the result, in a file-scope device array (one copy per GPU, held
+// until the process ends) instead of the context's work buffer.
+constexpr int kNoallocPartials = 1 << 18;                  // flux blocks: up to 2^26 slots
+constexpr int kNoallocChunks = kNoallocPartials / kChunk;
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) double scratch[kNoallocPartials + kNoallocChunks + 32];
+
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the device of the context's stream, looked
+// up once per device with that device current.  In host code the array's name
+// is only a stand-in: this address is what the kernels get.
+lbm_status scratch_on(hipStream_t stream, double** out) {
+  int dev = 0, cur = 0;
+  HIP_TRY(hipStreamGetDevice(stream, &dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(LBM_EINVAL, "device %d out of range", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    HIP_TRY(hipGetDevice(&cur));
+    if (cur != dev) HIP_TRY(hipSetDevice(dev));
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != dev) HIP_TRY(hipSetDevice(cur));
+    if (e != hipSuccess || !p)
+      return fail(LBM_EHIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    g_scratch_ptr[dev] = (double*)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return LBM_OK;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -435,6 +481,29 @@ lbm_status lbm_flux(lbm_ctx* c, double* q_out) {
   double q;
   lbm_status s = current_flux(c, &q);
   if (s != LBM_OK) return s;
+  *q_out = q;
+  if (!isfinite(q)) return fail(LBM_ENONFINITE, "flux is not finite");
+  return ok();
+}
+
+lbm_status lbm_flux_noalloc(lbm_ctx* c, double* q_out) {
+  if (!c || !q_out) return fail(LBM_EINVAL, "NULL argument");
+  const unsigned np = flux_partials(c);
+  if (np > (unsigned)kNoallocPartials)
+    return fail(LBM_EINVAL, "lbm_flux_noalloc: %llu slots exceed its scratch (at most %llu)",
+                (unsigned long long)c->n_slots, 256ull * kNoallocPartials);
+  double* sp = nullptr;
+  lbm_status s = scratch_on(c->stream, &sp);
+  if (s != LBM_OK) return s;
+  // every partial, chunk sum and the result are written before they are read:
+  // nothing in the scratch needs clearing
+  int n = 0;
+  s = dispatch<Flux>(c, sp, &n);
+  if (s != LBM_OK) return s;
+  double q;
+  s = reduce_partials(c, sp, sp + kNoallocPartials, sp + kNoallocPartials + kNoallocChunks, n, &q);
+  if (s != LBM_OK) return s;
+  q -= flux_pass_offset(c);
   *q_out = q;
   if (!isfinite(q)) return fail(LBM_ENONFINITE, "flux is not finite");
   return ok();

@@ -55,6 +55,7 @@ _SIGS = {
     "lbm_step": (_c.c_int, [_c.c_void_p, _c.c_int64]),
     "lbm_smooth": (_c.c_int, [_c.c_void_p, _c.c_int32]),
     "lbm_flux": (_c.c_int, [_c.c_void_p, _c.POINTER(_c.c_double)]),
+    "lbm_flux_noalloc": (_c.c_int, [_c.c_void_p, _c.POINTER(_c.c_double)]),
     "lbm_permeability": (_c.c_int, [_c.c_void_p, _c.POINTER(_c.c_double)]),
     "lbm_run_to_steady": (_c.c_int, [_c.c_void_p, _c.c_double, _c.c_int64,
                                      _c.POINTER(_c.c_int64), _c.POINTER(_c.c_double)]),
@@ -271,6 +272,12 @@ class Solver:
     def flux(self):
         q = ctypes.c_double(0.0)
         _check(self._lib.lbm_flux(self._h, ctypes.byref(q)))
+        return q.value
+
+    def flux_noalloc(self):
+        """lbm_flux_noalloc: the same flux with the library's own scratch."""
+        q = ctypes.c_double(0.0)
+        _check(self._lib.lbm_flux_noalloc(self._h, ctypes.byref(q)))
         return q.value
 
     def permeability(self):
