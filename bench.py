@@ -69,14 +69,38 @@ def cpu_baseline(Q, mask, tau, rho_in, rho_out, budget_s=12.0):
                       f"({dt:.1f} s wall)"}
 
 
+def _function_text(text, signature):
+    """Source text of the function that starts with `signature` (up to its
+    matching closing brace)."""
+    i = text.index(signature)
+    j = text.index("{", i)
+    depth = 0
+    for k in range(j, len(text)):
+        if text[k] == "{":
+            depth += 1
+        elif text[k] == "}":
+            depth -= 1
+            if depth == 0:
+                return text[i:k + 1]
+    raise ValueError(signature)
+
+
 def kernel_source_hash():
-    """Short hash of the step kernel's sources, to tie profiled counters to them."""
+    """Short hash of what fixes the step kernel's code and launch: its device
+    sources, the step arguments and grid, and the slot layout, so that
+    profiled counters are tied to them (host code elsewhere may change)."""
     import hashlib
+    csrc = os.path.join(ROOT, "paper_1609_09685_amd", "csrc")
     h = hashlib.sha256()
-    for f in ("kernels.h", "pull_index.h", "lattice.h", "context.h", "step_launch.h",
-              "step_launch.hip", "lbm_api.hip"):
-        with open(os.path.join(ROOT, "paper_1609_09685_amd", "csrc", f), "rb") as fh:
+    for f in ("kernels.h", "pull_index.h", "lattice.h", "step_launch.h", "step_launch.hip"):
+        with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
+    ctx = open(os.path.join(csrc, "context.h")).read()
+    api = open(os.path.join(csrc, "lbm_api.hip")).read()
+    for part in (_function_text(ctx, "StepArgs<T> step_args(const lbm_ctx* c)"),
+                 _function_text(ctx, "int step_grid(const lbm_ctx* c, const StepArgs<T>& a)"),
+                 _function_text(api, "lbm_status make_layout(const lbm_geom* g, Layout* L)")):
+        h.update(part.encode())
     return h.hexdigest()[:16]
 
 
