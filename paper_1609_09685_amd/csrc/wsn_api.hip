@@ -84,15 +84,22 @@ struct WgradPlan {
 
 WgradPlan wgrad_plan(int batch, int H, int W, int cin, int cout, int ks) {
   WgradPlan p;
-  // input-channel tile: 64 unless a 32-wide tile divides cin and a 64-wide
-  // one would leave a partly empty last tile (96 = 3 x 32, not 2 x 64)
-  p.tm = cin > 32 ? (cin % 64 != 0 && cin % 32 == 0 ? 32 : 64) : (cin > 16 ? 32 : 16);
-  p.nt = cout > 32 ? 64 : (cout > 16 ? 32 : 16);
+  if (ks == 3) {
+    // all nine taps per block (k_conv_wgrad3): 32 x 32 channel tiles, or 16
+    // where the layer is that narrow
+    p.tm = cin > 16 ? 32 : 16;
+    p.nt = cout > 16 ? 32 : 16;
+  } else {
+    // input-channel tile: 64 unless a 32-wide tile divides cin and a 64-wide
+    // one would leave a partly empty last tile (96 = 3 x 32, not 2 x 64)
+    p.tm = cin > 32 ? (cin % 64 != 0 && cin % 32 == 0 ? 32 : 64) : (cin > 16 ? 32 : 16);
+    p.nt = cout > 32 ? 64 : (cout > 16 ? 32 : 16);
+  }
   p.mtiles = (cin + p.tm - 1) / p.tm;
   p.ntiles = (cout + p.nt - 1) / p.nt;
   const long npix = (long)batch * H * W;
-  const long per_split = (long)ks * ks * p.mtiles * p.ntiles;
-  long want = (2048 + per_split - 1) / per_split;          // ~2048 blocks
+  const long per_split = (long)p.mtiles * p.ntiles;   // blocks per pixel split (taps: one block for 3x3, ks = 1 has one tap)
+  long want = ((ks == 3 ? 1024 : 2048) + per_split - 1) / per_split;   // blocks to fill the GPU
   const long chunks = (npix + 15) / 16;
   if (want > chunks) want = chunks;
   if (want < 1) want = 1;
@@ -112,8 +119,15 @@ size_t wgrad_bytes(const WgradPlan& p) {
 
 template <int KS, int TM, int NT>
 void launch_wgrad_t(const WgradArgs& a, const WgradPlan& p, hipStream_t st) {
-  const dim3 grid((unsigned)p.nsplit, (unsigned)(KS * KS * p.mtiles * p.ntiles));
-  k_conv_wgrad<KS, TM, NT><<<grid, kBlock, 0, st>>>(a);
+  if constexpr (KS == 3) {
+    if constexpr (TM <= 32 && NT <= 32) {
+      const dim3 grid((unsigned)p.nsplit, (unsigned)(p.mtiles * p.ntiles));
+      k_conv_wgrad3<TM, NT><<<grid, kBlock, 0, st>>>(a);
+    }
+  } else {
+    const dim3 grid((unsigned)p.nsplit, (unsigned)(KS * KS * p.mtiles * p.ntiles));
+    k_conv_wgrad<KS, TM, NT><<<grid, kBlock, 0, st>>>(a);
+  }
 }
 
 template <int KS, int TM>

@@ -14,9 +14,10 @@
 //                every tap reads its shifted window out of the one patch;
 //   data grad    the forward kernel on the output gradient with the weights
 //                flipped in space and transposed (w'[t][co][ci] = w[T-1-t][ci][co]);
-//   weight grad  M = ci, N = co, K = pixels, one tap per block, split over pixel
-//                ranges into partial sums that a second kernel adds in a fixed
-//                order (deterministic, no atomics).
+//   weight grad  M = ci, N = co, K = pixels, split over pixel ranges into
+//                partial sums that a second kernel adds in a fixed order
+//                (deterministic, no atomics); for 3x3 convolutions one block
+//                serves all nine taps from one staged input patch.
 // LDS row strides are 16 (mod 32) words, so the two halves of a wavefront's
 // operand reads fall on disjoint banks.
 #pragma once
@@ -252,6 +253,100 @@ __global__ __launch_bounds__(kBlock) void k_conv_wgrad(const WgradArgs a) {
         const int ci = m0 + (wm * G::FM + i) * 16 + 4 * kq + r;
         if (ci < a.cin) out[(size_t)ci * a.cout + co] = acc[i][j][r];
       }
+  }
+}
+
+// Weight gradient of a 3x3 convolution with all nine taps in one block:
+// dW[t][ci][co] = sum_p x[p + d_t][ci] dy[p][co] over the pixels p of split
+// blockIdx.x, channel tiles from blockIdx.y.  For every 16-pixel chunk of a row
+// the block stages the output gradient once and the input patch of rows
+// h - 1 .. h + 1, columns w0 - 1 .. w0 + 16 (zero outside the image); each tap
+// reads its shifted window of that one patch, so both operands are read once
+// per chunk instead of once per tap.  Partial sums go to
+// part[split][t][ci][co] (added in a fixed order by k_sum_splits).
+template <int TM, int NT>
+__global__ __launch_bounds__(kBlock) void k_conv_wgrad3(const WgradArgs a) {
+  using G = WaveGrid<TM / 16, NT / 16>;
+  constexpr int XS = lds_stride(TM), GS = lds_stride(NT);
+  __shared__ float xs[3][18][XS];
+  __shared__ float gs[16][GS];
+
+  const int mt = blockIdx.y % a.mtiles;
+  const int nt = blockIdx.y / a.mtiles;
+  const int m0 = mt * TM, n0 = nt * NT;
+  const int p_begin = blockIdx.x * a.sp;
+  const int p_end = min(p_begin + a.sp, a.npix);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wm = wave % G::WM, wn = wave / G::WM;
+  const bool active = wave < G::WM * G::WN;
+  const int kq = lane >> 4;
+
+  v4f acc[9][G::FM][G::FN];
+#pragma unroll
+  for (int t = 0; t < 9; ++t)
+#pragma unroll
+    for (int i = 0; i < G::FM; ++i)
+#pragma unroll
+      for (int j = 0; j < G::FN; ++j) acc[t][i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+
+  for (int p0 = p_begin; p0 < p_end; p0 += 16) {
+    // the chunk's row: image b, row h, columns w0 .. w0 + 15
+    const int w0 = p0 % a.W;
+    const int bh = p0 / a.W;
+    const int h = bh % a.H;
+    __syncthreads();
+    for (int e = threadIdx.x; e < 3 * 18 * TM; e += kBlock) {
+      const int m = e % TM, pc = (e / TM) % 18, pr = e / (18 * TM);
+      const int hs = h + pr - 1, ws = w0 + pc - 1, ci = m0 + m;
+      float v = 0.f;
+      if (hs >= 0 && hs < a.H && ws >= 0 && ws < a.W && ci < a.cin)
+        v = a.x[((size_t)(bh + pr - 1) * a.W + ws) * a.cin + ci];
+      xs[pr][pc][m] = v;
+    }
+    for (int e = threadIdx.x; e < 16 * NT; e += kBlock) {
+      const int n = e % NT, j = e / NT;
+      const int co = n0 + n;
+      float v = 0.f;
+      if (p0 + j < p_end && co < a.cout) v = a.dy[((size_t)p0 + j) * a.cout + co];
+      gs[j][n] = v;
+    }
+    __syncthreads();
+    if (active) {
+#pragma unroll
+      for (int kk = 0; kk < 16; kk += 4) {
+        float bv[G::FN];
+#pragma unroll
+        for (int j = 0; j < G::FN; ++j) bv[j] = gs[kk + kq][(wn * G::FN + j) * 16 + (lane & 15)];
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+          float av[G::FM];
+#pragma unroll
+          for (int i = 0; i < G::FM; ++i)
+            av[i] = xs[t / 3][kk + kq + t % 3][(wm * G::FM + i) * 16 + (lane & 15)];
+#pragma unroll
+          for (int i = 0; i < G::FM; ++i)
+#pragma unroll
+            for (int j = 0; j < G::FN; ++j) acc[t][i][j] = mfma4(av[i], bv[j], acc[t][i][j]);
+        }
+      }
+    }
+  }
+  if (!active) return;
+#pragma unroll
+  for (int t = 0; t < 9; ++t) {
+    float* out = a.part + ((size_t)blockIdx.x * 9 + t) * a.cin * a.cout;
+#pragma unroll
+    for (int j = 0; j < G::FN; ++j) {
+      const int co = n0 + (wn * G::FN + j) * 16 + (lane & 15);
+      if (co >= a.cout) continue;
+#pragma unroll
+      for (int i = 0; i < G::FM; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int ci = m0 + (wm * G::FM + i) * 16 + 4 * kq + r;
+          if (ci < a.cin) out[(size_t)ci * a.cout + co] = acc[t][i][j][r];
+        }
+    }
   }
 }
 
