@@ -45,26 +45,33 @@ def make_mask(Q, shape, porosity, seed=0):
     return qsgs_3d(nx, ny, nz, porosity, seed)
 
 
-def cpu_baseline(Q, mask, tau, rho_in, rho_out, budget_s=12.0):
-    """The CPU checker, as it stands, on a bounded sub-box of the workload."""
+def cpu_baseline(Q, mask, tau, rho_in, rho_out, budget_s=12.0, threads=None):
+    """The CPU checker, as it stands, on a bounded sub-box of the workload, with
+    `threads` OpenMP threads (None: all the host offers)."""
     import oracle
     if Q == 19:
         sub = np.ascontiguousarray(mask[:256, :256, :256])
     else:
         sub = mask
-    o = oracle.Oracle(Q, sub, tau, rho_in, rho_out)
-    o.step(1)
-    steps, t0 = 0, time.perf_counter()
-    while True:
+    prev = oracle.threads()
+    if threads is not None:
+        oracle.set_threads(threads)
+    try:
+        o = oracle.Oracle(Q, sub, tau, rho_in, rho_out)
         o.step(1)
-        steps += 1
-        dt = time.perf_counter() - t0
-        if dt >= budget_s or steps >= 10000:
-            break
+        steps, t0 = 0, time.perf_counter()
+        while True:
+            o.step(1)
+            steps += 1
+            dt = time.perf_counter() - t0
+            if dt >= budget_s or steps >= 10000:
+                break
+        used = oracle.threads()
+    finally:
+        oracle.set_threads(prev)
     n = sub.size
-    shape = "x".join(str(s) for s in (sub.shape[::-1] if sub.ndim == 3 else sub.shape[::-1]))
-    return {"value": n * steps / dt / 1e6, "unit": "MLUPS", "cores": oracle.threads(),
-            "kind": "oracle",
+    shape = "x".join(str(s) for s in sub.shape[::-1])
+    return {"value": n * steps / dt / 1e6, "unit": "MLUPS", "cores": used, "kind": "oracle",
             "sample": f"{steps} FP64 steps on the {shape} corner sub-box of the same mask "
                       f"({dt:.1f} s wall)"}
 
@@ -223,6 +230,7 @@ def bench_batch(args):
     ms_plain = e0.elapsed_time(e1) / steps
     alg_bytes = n_fluid * 2 * 9 * 4 + N
     achieved = alg_bytes / (ms_step / 1e3) / 1e9
+    to_steady = c3_to_steady(b, masks, taus, n_fluid) if args.to_steady else None
     out = {
         "metric": METRIC,
         "value": round(N * steps / (ms / 1e3) / 1e6, 1),
@@ -243,7 +251,49 @@ def bench_batch(args):
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                      "kernel": "k_step_batch", "algorithmic_bytes_per_launch": alg_bytes},
     }
+    if to_steady is not None:
+        out["to_steady"] = to_steady
     print(json.dumps(out), flush=True)
+
+
+def c3_to_steady(b, masks, taus, n_fluid, tol=1e-9, max_steps=3_000_000, n_check=4):
+    """Every sample of the batch from rest to the flux residual tol (K = 100):
+    wall time, outcome counts, the steps distribution, and, for n_check samples
+    spread over the batch, k and steps against the same solver run alone."""
+    import torch
+    from paper_1609_09685_amd import lbm
+    for s in b.solvers:
+        s.reset("uniform")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    status, steps, resid = b.run_to_steady(tol, max_steps)
+    k, kst = b.permeability()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ok = status == lbm.LBM_OK
+    log(f"to steady: {int(ok.sum())}/{b.n} converged in {wall:.1f} s")
+    updates = sum(s.n_fluid * int(n) for s, n in zip(b.solvers, steps))
+    picks = sorted({int(round(j)) for j in np.linspace(0, b.n - 1, n_check)})
+    checks = []
+    for j in picks:
+        s = lbm.Solver(masks[j], taus[j], 1.0005, 0.9995, precision=b.solvers[j].precision)
+        st, n1, _ = s.run_to_steady(tol, max_steps, raise_on_notconv=False)
+        k1 = s.permeability() if st else float("nan")
+        checks.append({"sample": j, "steps_batch": int(steps[j]), "steps_alone": int(n1),
+                       "k_batch": float(k[j]), "k_alone": float(k1),
+                       "bitwise_equal": bool(np.float64(k[j]).view(np.uint64) ==
+                                             np.float64(k1).view(np.uint64))})
+        s.close()
+    q = np.percentile(steps[ok], [0, 50, 90, 100]) if ok.any() else [0, 0, 0, 0]
+    return {"tol": tol, "wall_s": round(wall, 2), "converged": int(ok.sum()),
+            "not_converged": int((status == lbm.LBM_ENOTCONV).sum()),
+            "non_finite": int((status == lbm.LBM_ENONFINITE).sum()),
+            "non_finite_taus": [round(float(taus[j]), 4) for j in np.flatnonzero(
+                status == lbm.LBM_ENONFINITE)],
+            "steps_min_median_p90_max": [int(v) for v in q],
+            "fluid_node_updates": int(updates),
+            "mflups_over_run": round(updates / wall / 1e6, 1),
+            "single_run_checks": checks}
 
 
 def main():
@@ -259,6 +309,8 @@ def main():
     ap.add_argument("--batch", type=int, default=256, help="samples of the batched workload")
     ap.add_argument("--autotune", action="store_true", help="batched workload: tune tile orders")
     ap.add_argument("--no-graph", action="store_true", help="batched workload: plain launches")
+    ap.add_argument("--to-steady", action="store_true",
+                    help="batched workload: also run every sample to the 1e-9 residual")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU; the multi-GPU slab "
@@ -326,8 +378,9 @@ def main():
     out["stream_ceilings"] = stream_ceilings(arrays=Q)
     log(f"stream ceilings (GB/s): {out['stream_ceilings']}")
     if not args.no_cpu_baseline:
-        log("cpu baseline ...")
+        log("cpu baseline (all host threads, then one) ...")
         out["cpu_baseline"] = cpu_baseline(Q, mask, tau, rin, rout)
+        out["cpu_baseline"]["single_core"] = cpu_baseline(Q, mask, tau, rin, rout, threads=1)
     print(json.dumps(out), flush=True)
 
 
