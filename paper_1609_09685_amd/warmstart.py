@@ -273,6 +273,8 @@ def run_checked(masks, taus, start, precision, tol, max_steps, rerun_failed=True
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     start(b)
+    torch.cuda.synchronize()
+    sec_start = time.perf_counter() - t0
     start_steps = np.array([s.steps for s in b.solvers])
     status, steps, _, qlog = b.run_to_steady(tol, max_steps, log_windows=max_steps // K + 1)
     sec_main = time.perf_counter() - t0
@@ -303,7 +305,8 @@ def run_checked(masks, taus, start, precision, tol, max_steps, rerun_failed=True
         after(b)
     b.close()
     return dict(status=status.tolist(), steps=steps.tolist(), k=k.tolist(), seconds=sec,
-                seconds_to_residual=sec_main, steps_to_k_tol=acc.tolist(),
+                seconds_to_residual=sec_main, start_seconds=sec_start,
+                steps_to_k_tol=acc.tolist(),
                 one_step_change=one.tolist(), flagged=int(flagged.sum()), reruns=int(rerun.sum()))
 
 
@@ -325,14 +328,33 @@ def field_errors(pred_rho, pred_u, ref_rho, ref_u, solid, taus, u_scale):
     return out
 
 
+def step_seconds(mask, tau, precision, steps=2000):
+    """Wall time of one time step of one sample run alone (HIP events)."""
+    import torch
+    s = lbm.Solver(mask, tau, RHO_IN, RHO_OUT, precision=precision)
+    s.step(200)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    s.step(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    s.close()
+    return e0.elapsed_time(e1) / 1e3 / steps
+
+
 def evaluate(net, seeds, u_scale, tol=1e-9, max_steps=600000, precision="fp64", log=None):
     """Zero, linear-density and learned starts on the samples `seeds`: per-sample
-    steps and permeabilities, and the wall time of each batch job (the learned
-    start's includes inference, the field conversion and lbm_set_macro)."""
+    steps and permeabilities, the wall time of each batch job (the learned
+    start's includes inference, the field conversion and lbm_set_macro), and
+    per sample the time until its permeability stays within K_TOL of the
+    converged value, as if it ran alone: its steps to that point times the
+    step time of one sample alone, plus its share of the start's own work."""
     smp = [sample(s) for s in seeds]
     masks = [m for m, _, _ in smp]
     taus = [t for _, t, _ in smp]
     out = {"seeds": list(seeds), "tau": taus, "precision": precision}
+    out["step_seconds_alone"] = step_seconds(masks[0], taus[0], precision)
 
     def zero(b):
         pass
@@ -369,6 +391,10 @@ def evaluate(net, seeds, u_scale, tol=1e-9, max_steps=600000, precision="fp64", 
                                 rerun_failed=name != "zero",
                                 after=keep_fields if name == "zero" else None)
     out["learned"]["fallbacks"] = info["fallbacks"]
+    for name in ("zero", "linear", "learned"):
+        r = out[name]
+        r["seconds_to_k_tol"] = (np.array(r["steps_to_k_tol"]) * out["step_seconds_alone"] +
+                                 r["start_seconds"] / len(masks)).tolist()
     out["prediction_error"] = field_errors(info["pred"][0], info["pred"][1], ref["rho"], ref["u"],
                                            np.stack(masks), np.asarray(taus), u_scale)
     kz = np.array(out["zero"]["k"])
@@ -382,8 +408,10 @@ def evaluate(net, seeds, u_scale, tol=1e-9, max_steps=600000, precision="fp64", 
         for name in ("zero", "linear", "learned"):
             s = np.array(out[name]["steps"])
             a = np.array(out[name]["steps_to_k_tol"])
+            t = np.array(out[name]["seconds_to_k_tol"])
             log(f"{name:8s}: steps median {np.median(s):.0f} p90 {np.percentile(s, 90):.0f}, "
-                f"to k within {K_TOL:g}: median {np.median(a):.0f}, {out[name]['seconds']:.2f} s, "
-                f"reruns {out[name]['reruns']}")
+                f"to k within {K_TOL:g}: median {np.median(a):.0f} steps, "
+                f"{np.median(t) * 1e3:.1f} ms per sample alone (sum {t.sum():.2f} s); batch "
+                f"{out[name]['seconds']:.2f} s, reruns {out[name]['reruns']}")
         log(f"prediction error (network units): {out['prediction_error']}")
     return out

@@ -480,3 +480,24 @@ def test_wide_offsets_bitwise(Q, precision, case):
     assert (ba.flux() == bb.flux()).all()
     with pytest.raises(lbm.LBMError):
         lbm.Batch([solver(False), solver(True)])
+
+
+# FP32 deviation storage against FP64 at steady state on C2's 400x200 medium
+# (seed 0): within the 1e-4 bar from tau = 0.55 up; at tau = 0.51 the FP32 map
+# settles on its own fixed point about 1.5e-4 away (not a stopping effect:
+# 2e5 more steps or a 1e-11 residual do not move it; the same for density
+# drops 1e-4 .. 1e-2 and any deviation reference rho0), the FP32 limit near
+# tau = 1/2 that the design notes record.
+@pytest.mark.parametrize("tau,bar", [(0.51, 2e-4), (0.55, 1e-4), (0.6, 1e-4)])
+def test_fp32_tracks_fp64_near_tau_half(tau, bar):
+    m = qsgs_2d(400, 200, 0.74, 0)
+    ks = {}
+    for precision in ("fp64", "fp32"):
+        s = lbm.Solver(m, tau, 1.0005, 0.9995, precision=precision)
+        ok, steps, _ = s.run_to_steady(1e-9, 2_000_000)
+        assert ok
+        ks[precision] = s.permeability()
+        s.close()
+    rel = abs(ks["fp32"] - ks["fp64"]) / ks["fp64"]
+    print(f"tau {tau}: k fp64 {ks['fp64']:.10f} fp32 {ks['fp32']:.10f} rel {rel:.2e}")
+    assert rel <= bar, ks
