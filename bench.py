@@ -92,14 +92,16 @@ def _function_text(text, signature):
     raise ValueError(signature)
 
 
-def kernel_source_hash():
+def kernel_source_hash(extra=()):
     """Short hash of what fixes the step kernel's code and launch: its device
     sources, the step arguments and grid, and the slot layout, so that
-    profiled counters are tied to them (host code elsewhere may change)."""
+    profiled counters are tied to them (host code elsewhere may change).
+    `extra`: further source files of csrc/ (the batched launcher)."""
     import hashlib
     csrc = os.path.join(ROOT, "paper_1609_09685_amd", "csrc")
     h = hashlib.sha256()
-    for f in ("kernels.h", "pull_index.h", "lattice.h", "step_launch.h", "step_launch.hip"):
+    for f in ("kernels.h", "pull_index.h", "lattice.h", "step_launch.h", "step_launch.hip",
+              *extra):
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
     ctx = open(os.path.join(csrc, "context.h")).read()
@@ -111,10 +113,15 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def profiled_traffic(workload):
-    """HBM bytes per launch from the committed counter summary, if it was taken
-    on the current kernel sources (else None)."""
-    path = os.path.join(ROOT, "profiles", f"k_step_{workload}_pmc.md")
+BATCH_PROFILE = "k_step_batch_c3_fp32"     # counter summary of the batched workload
+BATCH_SOURCES = ("lbm_batch.hip",)
+
+
+def profiled_traffic(name, extra=()):
+    """HBM bytes per launch from the committed counter summary
+    profiles/<name>_pmc.md, if it was taken on the current kernel sources
+    (else None)."""
+    path = os.path.join(ROOT, "profiles", f"{name}_pmc.md")
     if not os.path.exists(path):
         return None
     fields = {}
@@ -124,7 +131,7 @@ def profiled_traffic(workload):
                                                               "kernel_source_sha256_16"):
                 k, v = line.split(":", 1)
                 fields[k.strip()] = v.strip()
-    if fields.get("kernel_source_sha256_16") != kernel_source_hash():
+    if fields.get("kernel_source_sha256_16") != kernel_source_hash(extra):
         return None
     return int(fields["traffic_bytes_per_launch"])
 
@@ -248,11 +255,16 @@ def bench_batch(args):
                    "ms_per_step_without_checks": round(ms_plain, 5),
                    "autotune": bool(args.autotune)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": profiled_traffic(BATCH_PROFILE, BATCH_SOURCES)
+                     if (b.n, args.autotune, args.no_graph) == (256, False, False) else None,
                      "kernel": "k_step_batch", "algorithmic_bytes_per_launch": alg_bytes},
     }
     if to_steady is not None:
         out["to_steady"] = to_steady
+    # the same probes as the headline, over 9 arrays of the batch's fluid size
+    out["stream_ceilings"] = stream_ceilings(n_per_array=n_fluid, arrays=9)
+    log(f"stream ceilings (GB/s): {out['stream_ceilings']}")
     print(json.dumps(out), flush=True)
 
 
@@ -371,7 +383,7 @@ def main():
                    "mflups": round(n_fluid * args.steps / (ms / 1e3) / 1e6, 1)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": profiled_traffic(args.workload)
+                     "traffic": profiled_traffic(f"k_step_{args.workload}")
                      if (args.band, args.xcd_remap) == (16, 1) else None,
                      "kernel": "k_step", "algorithmic_bytes_per_launch": alg_bytes},
     }

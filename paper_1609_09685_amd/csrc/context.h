@@ -70,7 +70,7 @@ struct lbm_ctx {
 
   uint64_t* bits() const { return (uint64_t*)(work + L.off_bits); }
   uint32_t* pfx() const { return (uint32_t*)(work + L.off_pfx); }
-  lbm::WordDesc* desc() const { return (lbm::WordDesc*)(work + L.off_desc); }
+  lbm::WordDesc* desc() const { return (lbm::WordDesc*)(work + L.off_desc); }   // D2Q9 only
   uint32_t* count() const { return (uint32_t*)(work + L.off_count); }
   uint32_t* scan() const { return (uint32_t*)(work + L.off_scan); }
   uint32_t* seg() const { return (uint32_t*)(work + L.off_seg); }
@@ -126,6 +126,8 @@ StepArgs<T> step_args(const lbm_ctx* c) {
   a.dst_g1 = a.dst + (uint64_t)split * c->L.ps;
   a.ps_bytes = off32_ok(c) ? (uint32_t)(c->L.ps * sizeof(T)) : 0u;
   a.desc = c->desc();
+  a.bits = c->bits();
+  a.pfx = c->pfx();
   a.bp_src = (const T*)c->bplane(c->parity);
   a.bp_dst = (T*)c->bplane(c->parity ^ 1);
   a.partial = c->partial();

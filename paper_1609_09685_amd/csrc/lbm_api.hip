@@ -5,7 +5,7 @@
 // Device memory is the caller's; the work buffer is carved here into
 //   bits     uint64 [nz][ny][nw + 2]     fluid bitmap with guard words
 //   pfx      uint32 [nz][ny][nw]         compact index of each word's first fluid node
-//   desc     WordDesc [nz][ny][nw]       per-word records read by the step kernel
+//   desc     WordDesc [nz][ny][nw]       per-word records read by the D2Q9 step kernels
 //   count    uint32 [nz][ny][nw]         fluid nodes per word (set-up only)
 //   scan     uint32 [scan blocks]        block totals of the prefix scan (set-up only)
 //   bplane   T [2 parities][2 sides][D+1][nz][ny]   edge-node moments
@@ -115,7 +115,7 @@ lbm_status make_layout(const lbm_geom* g, Layout* L) {
   L->off_pfx = off;
   off = align_up(off + nwords * 4, 256);
   L->off_desc = off;
-  off = align_up(off + nwords * sizeof(WordDesc), 256);
+  if (g->lattice == LBM_D2Q9) off = align_up(off + nwords * sizeof(WordDesc), 256);
   L->off_count = off;
   off = align_up(off + nwords * 4, 256);
   L->off_scan = off;
@@ -283,8 +283,10 @@ lbm_status build_fluid_map(lbm_ctx* c) {
   k_word_pfx<<<grid_1d(nwords), 256, 0, c->stream>>>(c->count(), c->seg(), c->pfx(), nwords, L.nw,
                                                       L.S, L.segs_per_row);
   HIP_TRY(hipGetLastError());
-  k_word_desc<<<grid_1d(nwords), 256, 0, c->stream>>>(c->fmap(), c->desc(), nwords);
-  HIP_TRY(hipGetLastError());
+  if (c->g.lattice == LBM_D2Q9) {
+    k_word_desc<<<grid_1d(nwords), 256, 0, c->stream>>>(c->fmap(), c->desc(), nwords);
+    HIP_TRY(hipGetLastError());
+  }
   uint64_t h[2] = {0, 0};
   HIP_TRY(hipMemcpyAsync(h, totals, sizeof h, hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));

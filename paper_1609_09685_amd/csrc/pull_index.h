@@ -10,10 +10,11 @@
 // .. 64 w + 63.  Fluid nodes get slots in x-fastest order; a row is cut into
 // segments of S words whose first slot sits on a 128-byte boundary, the slots
 // between the last fluid node of a segment and the next segment's first slot
-// being zero padding.  The step kernel reads one 16-byte record per word
-// (WordDesc): the slot of the word's first fluid node, the word's fluid bits,
-// and what a wavefront needs about the words on either side (whether node
-// 64 w - 1 / 64 w + 64 is fluid, and the padding between the words).
+// being zero padding.  The step kernel forms one record per word (WordDesc)
+// from the bitmap words and the slots of the words' first fluid nodes: the
+// slot of the word's first fluid node, the word's fluid bits, and what a
+// wavefront needs about the words on either side (whether node 64 w - 1 /
+// 64 w + 64 is fluid, and the padding between the words).
 //
 // Pull rules for direction i at a fluid node x (the readings of the paper's
 // boundary conditions): the source is x - c_i; (1) a source row outside the
@@ -37,7 +38,7 @@
 
 namespace lbm {
 
-// One word of one row, as the step kernel reads it (16 bytes, one scalar load).
+// One word of one row, as the step kernel sees it.
 struct WordDesc {
   uint32_t base;   // slot of the first fluid node at or after x = 64 w (next slot if none)
   uint32_t lo;     // fluid bits of x = 64 w .. 64 w + 31
