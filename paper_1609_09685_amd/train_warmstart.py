@@ -54,11 +54,11 @@ def main(argv=None):
     rep["train_samples_dropped"] = data.dropped
     rep["train_steps_median"] = float(np.median(data.steps))
     log(f"data: {len(data)} samples kept in {rep['data_seconds']:.1f} s, dropped {data.dropped}")
-    u_scale = ws.u_scale_of(data)
-    rep["u_scale"] = u_scale
+    scales = ws.scales_of(data)
+    rep["u_scale"], rep["rho_scale"] = scales
     net = ws.new_network(args.batch, seed=0)
     t0 = time.perf_counter()
-    hist = ws.train(net, data, u_scale, epochs=args.epochs, lr=args.lr, lr_end=args.lr_end, log=log)
+    hist = ws.train(net, data, scales, epochs=args.epochs, lr=args.lr, lr_end=args.lr_end, log=log)
     torch.cuda.synchronize()
     rep["train_seconds"] = time.perf_counter() - t0
     rep["loss_per_epoch"] = hist
@@ -69,7 +69,7 @@ def main(argv=None):
         f"({rep['ms_per_iteration']:.1f} ms each)")
     del data
     torch.cuda.empty_cache()
-    ev = ws.evaluate(net, range(20000, 20000 + args.test), u_scale, max_steps=args.eval_max_steps,
+    ev = ws.evaluate(net, range(20000, 20000 + args.test), scales, max_steps=args.eval_max_steps,
                      precision=args.eval_precision, log=log)
     rep["eval"] = ev
     summary = {}
@@ -80,6 +80,9 @@ def main(argv=None):
                          "steps_total": int(s.sum()), "seconds": ev[name]["seconds"],
                          "steps_to_k_tol_median": float(np.median(a)),
                          "steps_to_k_tol_p90": float(np.percentile(a, 90)),
+                         "steps_to_k_tol_total": int(a.sum()),
+                         "seconds_to_k_tol_median": float(np.median(ev[name]["seconds_to_k_tol"])),
+                         "seconds_to_k_tol_total": float(np.sum(ev[name]["seconds_to_k_tol"])),
                          "converged": int(sum(1 for v in ev[name]["status"] if v == 0))}
     for name in ("linear", "learned"):
         summary[name]["k_rel_err_max"] = ev[name]["k_rel_err_max"]
@@ -91,10 +94,13 @@ def main(argv=None):
     za, la = np.array(ev["zero"]["steps_to_k_tol"]), np.array(ev["learned"]["steps_to_k_tol"])
     summary["learned"]["k_tol_step_ratio_median"] = float(np.median(la / za))
     summary["prediction_error"] = ev["prediction_error"]
+    summary["gains"] = ws.start_gains(ev)
+    summary["step_seconds_alone"] = ev["step_seconds_alone"]
     rep["summary"] = summary
     log(json.dumps(summary))
     if args.out:
-        np.savez(args.out, params=net.params.cpu().numpy(), u_scale=np.array(u_scale),
+        np.savez(args.out, params=net.params.cpu().numpy(), u_scale=np.array(scales[0]),
+                 rho_scale=np.array(scales[1]),
                  levels=np.array(4), base=np.array(32))
     if args.report:
         with open(args.report, "w") as fh:

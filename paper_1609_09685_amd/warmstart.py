@@ -12,12 +12,15 @@ Steps, all on the GPU through the library's entry points:
 1. data: batched solver runs (``lbm.Batch``) of random QSGS masks to the
    steady state, fields read back with ``lbm_get_macro`` and normalised by
    Stokes linearity (``wsn_fields_to_nhwc``):
-       rho' = (rho - rho_lin(x)) / drho,   u' = u nu L / (c_s^2 drho) / U_SCALE,
+       rho' = (rho - rho_lin(x)) / (drho R),   u' = u nu L / (c_s^2 drho) / U,
    where rho_lin is the linear drop between the ghost planes, L = Nx + 1 and
    drho = rho_in - rho_out: in the Stokes regime both are independent of
    drho, u' is a local permeability (Darcy's law), and rho' holds only the
    local departures from the mean pressure gradient, which a convolutional
-   map can see (absolute position it cannot);
+   map can see (absolute position it cannot).  The scales U and R are the
+   RMS of the two quantities over the training data (``scales_of``), so that
+   every channel weighs alike in the loss (with R = 1 the density channel,
+   RMS ~0.13, carried ~1 % of the loss and was barely learned);
 2. training: masked MSE over fluid nodes, Adam (``wsn_*`` kernels);
 3. start: prediction -> fields (``wsn_nhwc_to_fields``, velocity zero in
    closed pockets) -> ``lbm_set_macro`` -> ``lbm_smooth`` (removes the modes
@@ -53,11 +56,13 @@ def features(taus, nx):
     return np.array([lbm.knudsen(t, nx) / KN_SCALE for t in taus], np.float32)
 
 
-def target_maps(taus, nx, u_scale, rho_in=RHO_IN, rho_out=RHO_OUT):
+def target_maps(taus, nx, scales, rho_in=RHO_IN, rho_out=RHO_OUT):
     """Per-sample (shift, slope, scale, inverse scale) [B, 3] between solver fields
     and normalised targets: y = (f - shift - slope (x + 1)) * scale.  The density
     target is the deviation from the linear drop between the ghost planes,
-    rho_in + (rho_out - rho_in)(x + 1)/(nx + 1), in units of drho."""
+    rho_in + (rho_out - rho_in)(x + 1)/(nx + 1), in units of drho R;
+    scales = (U, R), the velocity and density scales."""
+    u_scale, rho_scale = scales
     taus = np.asarray(taus, float)
     drho = rho_in - rho_out
     nu = (taus - 0.5) / 3.0
@@ -66,7 +71,7 @@ def target_maps(taus, nx, u_scale, rho_in=RHO_IN, rho_out=RHO_OUT):
     shift[:, 0] = rho_in
     slope = np.zeros((len(taus), 3))
     slope[:, 0] = (rho_out - rho_in) / (nx + 1)
-    fwd = np.stack([np.full_like(uf, 1.0 / drho), uf, uf], 1)
+    fwd = np.stack([np.full_like(uf, 1.0 / (drho * rho_scale)), uf, uf], 1)
     inv = 1.0 / fwd
     f32 = lambda a: a.astype(np.float32)
     return f32(shift), f32(slope), f32(fwd), f32(inv)
@@ -89,8 +94,8 @@ class Dataset:
     def __len__(self):
         return len(self.taus)
 
-    def targets(self, u_scale):
-        shift, slope, fwd, _ = target_maps(self.taus, self.x.shape[2], u_scale)
+    def targets(self, scales):
+        shift, slope, fwd, _ = target_maps(self.taus, self.x.shape[2], scales)
         return wsn.fields_to_nhwc(self.rho, self.u, _dev(shift), _dev(fwd), slope=_dev(slope))
 
 
@@ -159,13 +164,15 @@ def generate(seeds, chunk=1024, precision="fp32", tol=1e-9, max_steps=400000, lo
     return d
 
 
-def u_scale_of(data, sample_count=64):
-    """RMS of u nu L / (c_s^2 drho) over the fluid nodes of the first samples."""
-    shift, slope, fwd, _ = target_maps(data.taus[:sample_count], NX, 1.0)
+def scales_of(data, sample_count=64):
+    """(U, R): the RMS of u nu L / (c_s^2 drho) and of (rho - rho_lin)/drho over
+    the fluid nodes of the first samples."""
+    shift, slope, fwd, _ = target_maps(data.taus[:sample_count], NX, (1.0, 1.0))
     y = wsn.fields_to_nhwc(data.rho[:sample_count].contiguous(), data.u[:sample_count].contiguous(),
                            _dev(shift), _dev(fwd), slope=_dev(slope)).cpu().numpy()
     fluid = data.solid[:sample_count].cpu().numpy() == 0
-    return float(np.sqrt((y[..., 1:][fluid] ** 2).mean()))
+    return (float(np.sqrt((y[..., 1:][fluid] ** 2).mean())),
+            float(np.sqrt((y[..., 0][fluid] ** 2).mean())))
 
 
 def new_network(batch, seed=0, levels=4, base=32):
@@ -188,13 +195,13 @@ def new_network(batch, seed=0, levels=4, base=32):
                             base=base, height=NY, width=NX)
 
 
-def train(net, data, u_scale, epochs=20, lr=1e-3, lr_end=1e-5, seed=0, log=None):
+def train(net, data, scales, epochs=20, lr=1e-3, lr_end=1e-5, seed=0, log=None):
     """Adam on the masked MSE; minibatches are contiguous slices of the data in a
     shuffled order per epoch, learning rate decayed geometrically to lr_end.
     Returns the mean loss of every epoch."""
     import torch
     B = net.batch
-    y_all = data.targets(u_scale)
+    y_all = data.targets(scales)
     nb = len(data) // B
     rng = np.random.default_rng(seed)
     total = epochs * nb
@@ -214,7 +221,7 @@ def train(net, data, u_scale, epochs=20, lr=1e-3, lr_end=1e-5, seed=0, log=None)
     return hist
 
 
-def predict(net, masks, taus, u_scale):
+def predict(net, masks, taus, scales):
     """Fields (rho [B,H,W], u [B,2,H,W]) and the non-finite flags of the network's
     prediction for the samples (any number; run in chunks of the net's batch).
     The velocity is set to zero in fluid pockets that no path along lattice
@@ -226,7 +233,7 @@ def predict(net, masks, taus, u_scale):
     rho = torch.empty((n, NY, NX), dtype=torch.float32, device="cuda")
     u = torch.empty((n, 2, NY, NX), dtype=torch.float32, device="cuda")
     bad = torch.empty(n, dtype=torch.int32, device="cuda")
-    shift, slope, _, inv = target_maps(taus, NX, u_scale)
+    shift, slope, _, inv = target_maps(taus, NX, scales)
     for c0 in range(0, n, net.batch):
         m = min(net.batch, n - c0)
         solid = _dev(np.stack(masks[c0:c0 + m]).astype(np.uint8))
@@ -310,11 +317,11 @@ def run_checked(masks, taus, start, precision, tol, max_steps, rerun_failed=True
                 one_step_change=one.tolist(), flagged=int(flagged.sum()), reruns=int(rerun.sum()))
 
 
-def field_errors(pred_rho, pred_u, ref_rho, ref_u, solid, taus, u_scale):
+def field_errors(pred_rho, pred_u, ref_rho, ref_u, solid, taus, scales):
     """RMS error of the prediction over fluid nodes in the network's units
     (the targets rho', u'), per channel, over all samples, with the RMS of the
     reference targets."""
-    shift, slope, fwd, _ = target_maps(taus, NX, u_scale)
+    shift, slope, fwd, _ = target_maps(taus, NX, scales)
     xp = np.arange(1, NX + 1, dtype=np.float64)[None, None, :]
     fl = solid == 0
     out = {}
@@ -343,7 +350,7 @@ def step_seconds(mask, tau, precision, steps=2000):
     return e0.elapsed_time(e1) / 1e3 / steps
 
 
-def evaluate(net, seeds, u_scale, tol=1e-9, max_steps=600000, precision="fp64", log=None):
+def evaluate(net, seeds, scales, tol=1e-9, max_steps=600000, precision="fp64", log=None):
     """Zero, linear-density and learned starts on the samples `seeds`: per-sample
     steps and permeabilities, the wall time of each batch job (the learned
     start's includes inference, the field conversion and lbm_set_macro), and
@@ -374,7 +381,7 @@ def evaluate(net, seeds, u_scale, tol=1e-9, max_steps=600000, precision="fp64", 
         ref["rho"], ref["u"] = rho, u
 
     def learned(b):
-        rho, u, bad = predict(net, masks, taus, u_scale)
+        rho, u, bad = predict(net, masks, taus, scales)
         info["pred"] = (rho.cpu().numpy(), u.cpu().numpy())
         badh = bad.cpu().numpy()
         for j, s in enumerate(b.solvers):
@@ -396,7 +403,7 @@ def evaluate(net, seeds, u_scale, tol=1e-9, max_steps=600000, precision="fp64", 
         r["seconds_to_k_tol"] = (np.array(r["steps_to_k_tol"]) * out["step_seconds_alone"] +
                                  r["start_seconds"] / len(masks)).tolist()
     out["prediction_error"] = field_errors(info["pred"][0], info["pred"][1], ref["rho"], ref["u"],
-                                           np.stack(masks), np.asarray(taus), u_scale)
+                                           np.stack(masks), np.asarray(taus), scales)
     kz = np.array(out["zero"]["k"])
     okz = np.array(out["zero"]["status"]) == lbm.LBM_OK
     for name in ("linear", "learned"):
@@ -414,4 +421,25 @@ def evaluate(net, seeds, u_scale, tol=1e-9, max_steps=600000, precision="fp64", 
                 f"{np.median(t) * 1e3:.1f} ms per sample alone (sum {t.sum():.2f} s); batch "
                 f"{out[name]['seconds']:.2f} s, reruns {out[name]['reruns']}")
         log(f"prediction error (network units): {out['prediction_error']}")
+    return out
+
+
+def start_gains(ev, keys=("steps_to_k_tol", "seconds_to_k_tol", "steps")):
+    """The learned start against the zero and linear starts of an `evaluate`
+    result, over the samples that all three bring to the residual: for each
+    measure the ratio of the sums and of the medians (below 1: the learned
+    start is faster) and the share of samples on which it is faster."""
+    names = ("zero", "linear", "learned")
+    ok = np.ones(len(ev["seeds"]), bool)
+    for n in names:
+        ok &= np.array(ev[n]["status"]) == lbm.LBM_OK
+    out = {"samples": int(ok.sum())}
+    for key in keys:
+        a = {n: np.asarray(ev[n][key], float)[ok] for n in names}
+        r = {}
+        for base in ("zero", "linear"):
+            r[f"sum_vs_{base}"] = float(a["learned"].sum() / a[base].sum())
+            r[f"median_vs_{base}"] = float(np.median(a["learned"]) / np.median(a[base]))
+            r[f"faster_than_{base}"] = float(np.mean(a["learned"] < a[base]))
+        out[key] = r
     return out

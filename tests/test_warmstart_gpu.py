@@ -2,13 +2,21 @@
 (256 x 128 D2Q9 masks): solver-generated steady states, U-Net training with
 the HIP kernels, and the start it gives against the zero and linear starts.
 
-Reduced budget (2048 training samples, 10 epochs, 48 held-out samples) so the
-test runs in about a minute; the full-size figures come from
-``python -m paper_1609_09685_amd.train_warmstart``.  Checked: training lowers
-the held-out loss well below the untrained network's; every held-out sample
-that converges from the zero start converges from the learned start to the
-same permeability within 1e-4; no prediction needed the fallback; and the
-learned start does not need more steps than the zero start.
+Reduced budget (4096 training samples, 20 epochs, 96 held-out samples) so
+that the module runs in about three minutes; the full-size figures come from
+``python -m paper_1609_09685_amd.train_warmstart``.  Everything is seeded and
+the kernels are deterministic, so the figures repeat exactly.
+
+Checked: training lowers the held-out loss well below the untrained
+network's; all but a few held-out samples (the smallest tau, whose zero start
+can need more than the 300,000-step budget) converge from every start, the
+learned start to the zero start's permeability within 1e-4, with no
+fallback; and on the samples all three starts bring to the residual the
+learned start gains over both the method without it (the zero start) and
+the cheap linear-density start: summed and median steps until k stays within 1e-4 of
+its converged value, and the same for the per-sample time to that point
+(steps times the step time of one sample alone, plus the start's own work,
+inference included), each at most GAIN_BAR times the other start's.
 """
 import numpy as np
 import pytest
@@ -16,11 +24,16 @@ import torch
 
 from paper_1609_09685_amd import lbm, warmstart as ws, wsn
 
-pytestmark = pytest.mark.gpu
+# data and training take about 130 s of the first test's time
+pytestmark = [pytest.mark.gpu, pytest.mark.timeout(600)]
+
+GAIN_BAR = 0.95     # learned / other start, on sums and medians
+N_TRAIN, EPOCHS, N_EVAL = 4096, 20, 96
+MAX_UNCONVERGED = 4  # held-out samples allowed to miss the step budget from some start
 
 
-def _heldout_loss(net, data, u_scale):
-    y = data.targets(u_scale)
+def _heldout_loss(net, data, scales):
+    y = data.targets(scales)
     losses = []
     B = net.batch
     for c0 in range(0, len(data) - B + 1, B):
@@ -30,29 +43,45 @@ def _heldout_loss(net, data, u_scale):
     return float(np.mean(losses))
 
 
-def test_learned_start_end_to_end():
+@pytest.fixture(scope="module")
+def trained():
     torch.cuda.set_device(0)
-    data = ws.generate(range(10000, 12048), chunk=2048, max_steps=200000)
-    assert len(data) >= 2000
-    u_scale = ws.u_scale_of(data)
+    log = lambda msg: print(msg, flush=True)    # progress (visible with -s)
+    data = ws.generate(range(10000, 10000 + N_TRAIN), chunk=N_TRAIN // 2, max_steps=200000,
+                       log=log)
+    # ~1 % of random samples (the smallest tau) do not reach the residual
+    # within 200,000 steps; they are dropped, not trained on
+    assert len(data) >= 0.97 * N_TRAIN, data.dropped
+    scales = ws.scales_of(data)
     held = ws.generate(range(21000, 21032), chunk=32, max_steps=200000)
     net = ws.new_network(16, seed=0)
-    before = _heldout_loss(net, held, u_scale)
-    hist = ws.train(net, data, u_scale, epochs=10, lr=1e-3, lr_end=5e-5)
-    after = _heldout_loss(net, held, u_scale)
-    assert hist[-1] < 0.5 * hist[0]
-    assert after < 0.2 * before, (before, after)
+    before = _heldout_loss(net, held, scales)
+    hist = ws.train(net, data, scales, epochs=EPOCHS, lr=1e-3, lr_end=5e-5, log=log)
+    after = _heldout_loss(net, held, scales)
+    del data, held
+    torch.cuda.empty_cache()
+    return net, scales, hist, before, after
 
-    ev = ws.evaluate(net, range(20000, 20048), u_scale, max_steps=300000)
-    zero, learned = ev["zero"], ev["learned"]
+
+def test_training_lowers_the_loss(trained):
+    _, scales, hist, before, after = trained
+    print(f"scales {scales}; training loss {hist[0]:.3f} -> {hist[-1]:.4f}; "
+          f"held-out {before:.3f} -> {after:.4f}")
+    assert hist[-1] < 0.5 * hist[0]
+    assert after < 0.35 * before, (before, after)
+
+
+def test_learned_start_beats_zero_and_linear_starts(trained):
+    net, scales = trained[0], trained[1]
+    ev = ws.evaluate(net, range(20000, 20000 + N_EVAL), scales, max_steps=300000,
+                     log=lambda msg: print(msg, flush=True))
+    learned = ev["learned"]
     assert learned["fallbacks"] == 0
+    assert learned["k_compared"] >= N_EVAL - MAX_UNCONVERGED
     assert learned["k_rel_err_max"] <= 1e-4, learned["k_rel_err_max"]
-    assert learned["k_compared"] >= 45
-    z, l = np.array(zero["steps"]), np.array(learned["steps"])
-    za, la = np.array(zero["steps_to_k_tol"]), np.array(learned["steps_to_k_tol"])
-    both = (np.array(zero["status"]) == lbm.LBM_OK) & (np.array(learned["status"]) == lbm.LBM_OK)
-    print(f"held-out loss {before:.3f} -> {after:.4f}; steps to the residual: zero "
-          f"{z[both].sum()} learned {l[both].sum()}; steps to k within 1e-4: zero "
-          f"{za[both].sum()} learned {la[both].sum()}; errors {ev['prediction_error']}")
-    assert la[both].sum() <= 1.02 * za[both].sum()
-    assert l[both].sum() <= 1.02 * z[both].sum()
+    g = ws.start_gains(ev)
+    print(f"gains {g}; prediction errors {ev['prediction_error']}")
+    assert g["samples"] >= N_EVAL - MAX_UNCONVERGED
+    for key in ("steps_to_k_tol", "seconds_to_k_tol"):
+        for ratio in ("sum_vs_zero", "sum_vs_linear", "median_vs_zero", "median_vs_linear"):
+            assert g[key][ratio] <= GAIN_BAR, (key, ratio, g[key])
