@@ -262,14 +262,19 @@ __global__ __launch_bounds__(kBlock) void k_conv_wgrad(const WgradArgs a) {
 // the block stages the output gradient once and the input patch of rows
 // h - 1 .. h + 1, columns w0 - 1 .. w0 + 16 (zero outside the image); each tap
 // reads its shifted window of that one patch, so both operands are read once
-// per chunk instead of once per tap.  Partial sums go to
-// part[split][t][ci][co] (added in a fixed order by k_sum_splits).
+// per chunk instead of once per tap.  The staging is double-buffered: the
+// loads of the next chunk are issued before the matrix-core work on this one
+// and written to the other LDS buffer after it, one barrier per chunk.
+// Partial sums go to part[split][t][ci][co] (added in a fixed order by
+// k_sum_splits).
 template <int TM, int NT>
 __global__ __launch_bounds__(kBlock) void k_conv_wgrad3(const WgradArgs a) {
   using G = WaveGrid<TM / 16, NT / 16>;
   constexpr int XS = lds_stride(TM), GS = lds_stride(NT);
-  __shared__ float xs[3][18][XS];
-  __shared__ float gs[16][GS];
+  constexpr int XN = 3 * 18 * TM, GN = 16 * NT;   // staged values per chunk
+  constexpr int XR = (XN + kBlock - 1) / kBlock, GR = (GN + kBlock - 1) / kBlock;
+  __shared__ float xs[2][3][18][XS];
+  __shared__ float gs[2][16][GS];
 
   const int mt = blockIdx.y % a.mtiles;
   const int nt = blockIdx.y / a.mtiles;
@@ -281,6 +286,45 @@ __global__ __launch_bounds__(kBlock) void k_conv_wgrad3(const WgradArgs a) {
   const bool active = wave < G::WM * G::WN;
   const int kq = lane >> 4;
 
+  // a chunk's values in registers: input patch, then output gradient
+  float xr[XR], gr[GR];
+  auto fetch = [&](int p0) {
+    const int w0 = p0 % a.W;   // the chunk's row: image b, row h, columns w0 .. w0 + 15
+    const int bh = p0 / a.W;
+    const int h = bh % a.H;
+#pragma unroll
+    for (int k = 0; k < XR; ++k) {
+      const int e = threadIdx.x + k * kBlock;
+      const int m = e % TM, pc = (e / TM) % 18, pr = e / (18 * TM);
+      const int hs = h + pr - 1, ws = w0 + pc - 1, ci = m0 + m;
+      float v = 0.f;
+      if (e < XN && hs >= 0 && hs < a.H && ws >= 0 && ws < a.W && ci < a.cin)
+        v = a.x[((size_t)(bh + pr - 1) * a.W + ws) * a.cin + ci];
+      xr[k] = v;
+    }
+#pragma unroll
+    for (int k = 0; k < GR; ++k) {
+      const int e = threadIdx.x + k * kBlock;
+      const int n = e % NT, j = e / NT;
+      const int co = n0 + n;
+      float v = 0.f;
+      if (e < GN && p0 + j < p_end && co < a.cout) v = a.dy[((size_t)p0 + j) * a.cout + co];
+      gr[k] = v;
+    }
+  };
+  auto stash = [&](int b) {
+#pragma unroll
+    for (int k = 0; k < XR; ++k) {
+      const int e = threadIdx.x + k * kBlock;
+      if (e < XN) xs[b][e / (18 * TM)][(e / TM) % 18][e % TM] = xr[k];
+    }
+#pragma unroll
+    for (int k = 0; k < GR; ++k) {
+      const int e = threadIdx.x + k * kBlock;
+      if (e < GN) gs[b][e / NT][e % NT] = gr[k];
+    }
+  };
+
   v4f acc[9][G::FM][G::FN];
 #pragma unroll
   for (int t = 0; t < 9; ++t)
@@ -289,40 +333,28 @@ __global__ __launch_bounds__(kBlock) void k_conv_wgrad3(const WgradArgs a) {
 #pragma unroll
       for (int j = 0; j < G::FN; ++j) acc[t][i][j] = v4f{0.f, 0.f, 0.f, 0.f};
 
+  if (p_begin < p_end) {
+    fetch(p_begin);
+    stash(0);
+  }
+  __syncthreads();
+  int buf = 0;
   for (int p0 = p_begin; p0 < p_end; p0 += 16) {
-    // the chunk's row: image b, row h, columns w0 .. w0 + 15
-    const int w0 = p0 % a.W;
-    const int bh = p0 / a.W;
-    const int h = bh % a.H;
-    __syncthreads();
-    for (int e = threadIdx.x; e < 3 * 18 * TM; e += kBlock) {
-      const int m = e % TM, pc = (e / TM) % 18, pr = e / (18 * TM);
-      const int hs = h + pr - 1, ws = w0 + pc - 1, ci = m0 + m;
-      float v = 0.f;
-      if (hs >= 0 && hs < a.H && ws >= 0 && ws < a.W && ci < a.cin)
-        v = a.x[((size_t)(bh + pr - 1) * a.W + ws) * a.cin + ci];
-      xs[pr][pc][m] = v;
-    }
-    for (int e = threadIdx.x; e < 16 * NT; e += kBlock) {
-      const int n = e % NT, j = e / NT;
-      const int co = n0 + n;
-      float v = 0.f;
-      if (p0 + j < p_end && co < a.cout) v = a.dy[((size_t)p0 + j) * a.cout + co];
-      gs[j][n] = v;
-    }
-    __syncthreads();
+    const bool more = p0 + 16 < p_end;   // uniform
+    if (more) fetch(p0 + 16);
     if (active) {
 #pragma unroll
       for (int kk = 0; kk < 16; kk += 4) {
         float bv[G::FN];
 #pragma unroll
-        for (int j = 0; j < G::FN; ++j) bv[j] = gs[kk + kq][(wn * G::FN + j) * 16 + (lane & 15)];
+        for (int j = 0; j < G::FN; ++j)
+          bv[j] = gs[buf][kk + kq][(wn * G::FN + j) * 16 + (lane & 15)];
 #pragma unroll
         for (int t = 0; t < 9; ++t) {
           float av[G::FM];
 #pragma unroll
           for (int i = 0; i < G::FM; ++i)
-            av[i] = xs[t / 3][kk + kq + t % 3][(wm * G::FM + i) * 16 + (lane & 15)];
+            av[i] = xs[buf][t / 3][kk + kq + t % 3][(wm * G::FM + i) * 16 + (lane & 15)];
 #pragma unroll
           for (int i = 0; i < G::FM; ++i)
 #pragma unroll
@@ -330,6 +362,10 @@ __global__ __launch_bounds__(kBlock) void k_conv_wgrad3(const WgradArgs a) {
         }
       }
     }
+    // the other buffer was last read before the previous barrier
+    if (more) stash(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
   }
   if (!active) return;
 #pragma unroll
