@@ -104,16 +104,32 @@ __global__ __launch_bounds__(kBlock) void k_conv_fwd(const ConvArgs a) {
   }
   const int kq = lane >> 4;
 
-  for (int c0 = 0; c0 < a.cin; c0 += kCK) {
-    __syncthreads();
-    for (int e = threadIdx.x; e < NP * kCK; e += kBlock) {
+  // The input patch of one chunk of kCK channels in registers: the next
+  // chunk's patch loads are issued right after this chunk is in LDS, so they
+  // are in flight during its matrix-core work.  The weights, read by every
+  // block and mostly found in the L2, are staged directly.
+  constexpr int XR = (PMAX * kCK + kBlock - 1) / kBlock;
+  float xr[XR];
+  auto fetch = [&](int c0) {
+#pragma unroll
+    for (int k = 0; k < XR; ++k) {
+      const int e = threadIdx.x + k * kBlock;
       const int c = e % kCK, p = e / kCK;
       const int pr = p / PC, pc = p - pr * PC;
       const int h = h0 - R + pr, w = w0 - R + pc, ci = c0 + c;
       float v = 0.f;
-      if (h >= 0 && h < a.H && w >= 0 && w < a.W && ci < a.cin)
+      if (e < NP * kCK && h >= 0 && h < a.H && w >= 0 && w < a.W && ci < a.cin)
         v = a.x[((img + h) * a.W + w) * a.cin + ci];
-      xs[c][p] = v;
+      xr[k] = v;
+    }
+  };
+  fetch(0);
+  for (int c0 = 0; c0 < a.cin; c0 += kCK) {
+    __syncthreads();   // the previous chunk's reads of xs / ws are done
+#pragma unroll
+    for (int k = 0; k < XR; ++k) {
+      const int e = threadIdx.x + k * kBlock;
+      if (e < NP * kCK) xs[e % kCK][e / kCK] = xr[k];
     }
     for (int e = threadIdx.x; e < T * kCK * NT; e += kBlock) {
       const int n = e % NT, c = (e / NT) % kCK, t = e / (NT * kCK);
@@ -123,6 +139,7 @@ __global__ __launch_bounds__(kBlock) void k_conv_fwd(const ConvArgs a) {
       ws[t][c][n] = v;
     }
     __syncthreads();
+    if (c0 + kCK < a.cin) fetch(c0 + kCK);   // uniform
     if (active) {
 #pragma unroll
       for (int t = 0; t < T; ++t) {
