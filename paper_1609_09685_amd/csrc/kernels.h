@@ -784,12 +784,32 @@ __global__ __launch_bounds__(kThreads) __attribute__((
 // owner[b].y of the domain's own launch would: the tile orders carry over.
 // args[2 d + flip] holds the arguments of domain d for this step (the two
 // entries of a domain differ by the ping-pong parity).
+// p, re-derived through the global address space: a pointer loaded from
+// memory is generic to the compiler (flat loads and stores, vector loads of
+// uniform values); the cast lets it use global and scalar memory
+// instructions, as it does for pointers passed as kernel arguments.
+template <class P>
+__device__ __forceinline__ P* in_global(P* p) {
+  return (P*)(__attribute__((address_space(1))) P*)(uintptr_t)p;
+}
+
 template <class L, class T, bool FLUX, bool LINEAR, bool OFF32, bool PER, bool TRT>
 __global__ __launch_bounds__(kThreads) void k_step_batch(const StepArgs<T>* __restrict__ args,
                                                          const int2* __restrict__ owner, int flip) {
   const int2 o = owner[blockIdx.x];
   if (o.x < 0) return;   // whole block
-  const StepArgs<T> a = args[2 * o.x + flip];
+  StepArgs<T> a = args[2 * o.x + flip];
+  // every buffer of a context is device memory
+  a.src = in_global(a.src);
+  a.dst = in_global(a.dst);
+  a.src_g1 = in_global(a.src_g1);
+  a.dst_g1 = in_global(a.dst_g1);
+  a.desc = in_global(a.desc);
+  a.bits = in_global(a.bits);
+  a.pfx = in_global(a.pfx);
+  a.bp_src = in_global(a.bp_src);
+  a.bp_dst = in_global(a.bp_dst);
+  a.partial = in_global(a.partial);
   step_tile<L, T, FLUX, LINEAR, OFF32, PER, TRT>(a, (uint32_t)o.y);
 }
 
