@@ -94,8 +94,9 @@ def _function_text(text, signature):
 
 def kernel_source_hash(extra=()):
     """Short hash of what fixes the step kernel's code and launch: its device
-    sources, the step arguments and grid, and the slot layout, so that
-    profiled counters are tied to them (host code elsewhere may change).
+    sources, its compiler flags, the step arguments and grid, and the slot
+    layout, so that profiled counters are tied to them (host code elsewhere
+    may change).
     `extra`: further source files of csrc/ (the batched launcher)."""
     import hashlib
     csrc = os.path.join(ROOT, "paper_1609_09685_amd", "csrc")
@@ -106,6 +107,8 @@ def kernel_source_hash(extra=()):
             h.update(fh.read())
     ctx = open(os.path.join(csrc, "context.h")).read()
     api = open(os.path.join(csrc, "lbm_api.hip")).read()
+    from paper_1609_09685_amd import build as _b
+    h.update(repr((_b.HIPCC_FLAGS, _b.STEP_FLAGS)).encode())   # how the step objects are compiled
     for part in (_function_text(ctx, "StepArgs<T> step_args(const lbm_ctx* c)"),
                  _function_text(ctx, "int step_grid(const lbm_ctx* c, const StepArgs<T>& a)"),
                  _function_text(api, "lbm_status make_layout(const lbm_geom* g, Layout* L)")):
