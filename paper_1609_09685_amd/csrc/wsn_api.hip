@@ -43,7 +43,10 @@ lbm_status check_conv(int32_t batch, int32_t height, int32_t width, int32_t cin,
 template <int KS, int NT>
 void launch_fwd_t(const ConvArgs& a, int batch, hipStream_t st) {
   const dim3 grid((unsigned)(batch * a.tiles_h * a.tiles_w), (unsigned)((a.cout + NT - 1) / NT));
-  k_conv_fwd<KS, NT><<<grid, kBlock, 0, st>>>(a);
+  const bool v4 = a.cin % 4 == 0 && a.cout % 4 == 0 && ((uintptr_t)a.x & 15u) == 0 &&
+                  ((uintptr_t)a.w & 15u) == 0;
+  if (v4) k_conv_fwd<KS, NT, true><<<grid, kBlock, 0, st>>>(a);
+  else k_conv_fwd<KS, NT, false><<<grid, kBlock, 0, st>>>(a);
 }
 
 void conv_fwd(const float* x, const float* w, const float* bias, float* y, int batch, int H, int W,

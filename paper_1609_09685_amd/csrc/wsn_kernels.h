@@ -63,7 +63,9 @@ struct ConvArgs {
   int relu;
 };
 
-template <int KS, int NT>
+// V4: cin and cout are multiples of 4 and x, w are 16-byte aligned, so the
+// staging moves four channels per load (the channel runs are contiguous).
+template <int KS, int NT, bool V4>
 __global__ __launch_bounds__(kBlock) void k_conv_fwd(const ConvArgs a) {
   constexpr int R = KS / 2, T = KS * KS;
   using G = WaveGrid<kTile / 16, NT / 16>;
@@ -73,7 +75,7 @@ __global__ __launch_bounds__(kBlock) void k_conv_fwd(const ConvArgs a) {
                            : (4 + 2 * R) * (16 + 2 * R);
   constexpr int PS = lds_stride(PMAX), NS = lds_stride(NT);
   __shared__ float xs[kCK][PS];
-  __shared__ float ws[T][kCK][NS];
+  __shared__ __attribute__((aligned(16))) float ws[T][kCK][NS];
 
   const int tw = 1 << a.tw_log2;
   const int tile = blockIdx.x;
@@ -108,35 +110,71 @@ __global__ __launch_bounds__(kBlock) void k_conv_fwd(const ConvArgs a) {
   // chunk's patch loads are issued right after this chunk is in LDS, so they
   // are in flight during its matrix-core work.  The weights, read by every
   // block and mostly found in the L2, are staged directly.
-  constexpr int XR = (PMAX * kCK + kBlock - 1) / kBlock;
-  float xr[XR];
+  constexpr int XR = V4 ? (PMAX * (kCK / 4) + kBlock - 1) / kBlock : (PMAX * kCK + kBlock - 1) / kBlock;
+  v4f xr[V4 ? XR : 1];
+  float xs1[V4 ? 1 : XR];
   auto fetch = [&](int c0) {
+    if constexpr (V4) {
 #pragma unroll
-    for (int k = 0; k < XR; ++k) {
-      const int e = threadIdx.x + k * kBlock;
-      const int c = e % kCK, p = e / kCK;
-      const int pr = p / PC, pc = p - pr * PC;
-      const int h = h0 - R + pr, w = w0 - R + pc, ci = c0 + c;
-      float v = 0.f;
-      if (e < NP * kCK && h >= 0 && h < a.H && w >= 0 && w < a.W && ci < a.cin)
-        v = a.x[((img + h) * a.W + w) * a.cin + ci];
-      xr[k] = v;
+      for (int k = 0; k < XR; ++k) {
+        const int e = threadIdx.x + k * kBlock;   // (pixel, group of 4 channels)
+        const int cq = e % (kCK / 4), p = e / (kCK / 4);
+        const int pr = p / PC, pc = p - pr * PC;
+        const int h = h0 - R + pr, w = w0 - R + pc, ci = c0 + 4 * cq;
+        v4f v = v4f{0.f, 0.f, 0.f, 0.f};
+        if (e < NP * (kCK / 4) && h >= 0 && h < a.H && w >= 0 && w < a.W && ci < a.cin)
+          v = *(const v4f*)(a.x + ((img + h) * a.W + w) * a.cin + ci);
+        xr[k] = v;
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < XR; ++k) {
+        const int e = threadIdx.x + k * kBlock;
+        const int c = e % kCK, p = e / kCK;
+        const int pr = p / PC, pc = p - pr * PC;
+        const int h = h0 - R + pr, w = w0 - R + pc, ci = c0 + c;
+        float v = 0.f;
+        if (e < NP * kCK && h >= 0 && h < a.H && w >= 0 && w < a.W && ci < a.cin)
+          v = a.x[((img + h) * a.W + w) * a.cin + ci];
+        xs1[k] = v;
+      }
     }
   };
   fetch(0);
   for (int c0 = 0; c0 < a.cin; c0 += kCK) {
     __syncthreads();   // the previous chunk's reads of xs / ws are done
+    if constexpr (V4) {
 #pragma unroll
-    for (int k = 0; k < XR; ++k) {
-      const int e = threadIdx.x + k * kBlock;
-      if (e < NP * kCK) xs[e % kCK][e / kCK] = xr[k];
-    }
-    for (int e = threadIdx.x; e < T * kCK * NT; e += kBlock) {
-      const int n = e % NT, c = (e / NT) % kCK, t = e / (NT * kCK);
-      const int ci = c0 + c, co = n0 + n;
-      float v = 0.f;
-      if (ci < a.cin && co < a.cout) v = a.w[((size_t)t * a.cin + ci) * a.cout + co];
-      ws[t][c][n] = v;
+      for (int k = 0; k < XR; ++k) {
+        const int e = threadIdx.x + k * kBlock;
+        if (e < NP * (kCK / 4)) {
+          const int cq = e % (kCK / 4), p = e / (kCK / 4);
+          xs[4 * cq + 0][p] = xr[k].x;
+          xs[4 * cq + 1][p] = xr[k].y;
+          xs[4 * cq + 2][p] = xr[k].z;
+          xs[4 * cq + 3][p] = xr[k].w;
+        }
+      }
+      for (int e = threadIdx.x; e < T * kCK * (NT / 4); e += kBlock) {
+        const int n4 = e % (NT / 4), c = (e / (NT / 4)) % kCK, t = e / ((NT / 4) * kCK);
+        const int ci = c0 + c, co = n0 + 4 * n4;
+        v4f v = v4f{0.f, 0.f, 0.f, 0.f};
+        if (ci < a.cin && co < a.cout) v = *(const v4f*)(a.w + ((size_t)t * a.cin + ci) * a.cout + co);
+        *(v4f*)&ws[t][c][4 * n4] = v;
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < XR; ++k) {
+        const int e = threadIdx.x + k * kBlock;
+        if (e < NP * kCK) xs[e % kCK][e / kCK] = xs1[k];
+      }
+      for (int e = threadIdx.x; e < T * kCK * NT; e += kBlock) {
+        const int n = e % NT, c = (e / NT) % kCK, t = e / (NT * kCK);
+        const int ci = c0 + c, co = n0 + n;
+        float v = 0.f;
+        if (ci < a.cin && co < a.cout) v = a.w[((size_t)t * a.cin + ci) * a.cout + co];
+        ws[t][c][n] = v;
+      }
     }
     __syncthreads();
     if (c0 + kCK < a.cin) fetch(c0 + kCK);   // uniform
