@@ -125,7 +125,10 @@ void launch_wgrad_t(const WgradArgs& a, const WgradPlan& p, hipStream_t st) {
   if constexpr (KS == 3) {
     if constexpr (TM <= 32 && NT <= 32) {
       const dim3 grid((unsigned)p.nsplit, (unsigned)(p.mtiles * p.ntiles));
-      k_conv_wgrad3<TM, NT><<<grid, kBlock, 0, st>>>(a);
+      const bool v4 = a.cin % 4 == 0 && a.cout % 4 == 0 && ((uintptr_t)a.x & 15u) == 0 &&
+                      ((uintptr_t)a.dy & 15u) == 0;
+      if (v4) k_conv_wgrad3<TM, NT, true><<<grid, kBlock, 0, st>>>(a);
+      else k_conv_wgrad3<TM, NT, false><<<grid, kBlock, 0, st>>>(a);
     }
   } else {
     const dim3 grid((unsigned)p.nsplit, (unsigned)(KS * KS * p.mtiles * p.ntiles));

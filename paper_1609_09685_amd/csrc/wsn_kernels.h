@@ -23,6 +23,8 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 #include <stdint.h>
 
 namespace wsn {
@@ -322,14 +324,18 @@ __global__ __launch_bounds__(kBlock) void k_conv_wgrad(const WgradArgs a) {
 // and written to the other LDS buffer after it, one barrier per chunk.
 // Partial sums go to part[split][t][ci][co] (added in a fixed order by
 // k_sum_splits).
-template <int TM, int NT>
+// V4: cin and cout are multiples of 4 and x, dy are 16-byte aligned, so the
+// staging moves four channels per load.
+template <int TM, int NT, bool V4>
 __global__ __launch_bounds__(kBlock) void k_conv_wgrad3(const WgradArgs a) {
   using G = WaveGrid<TM / 16, NT / 16>;
   constexpr int XS = lds_stride(TM), GS = lds_stride(NT);
-  constexpr int XN = 3 * 18 * TM, GN = 16 * NT;   // staged values per chunk
+  constexpr int VW = V4 ? 4 : 1;                      // channels per staged value
+  constexpr int XN = 3 * 18 * TM / VW, GN = 16 * NT / VW;   // staged values per chunk
   constexpr int XR = (XN + kBlock - 1) / kBlock, GR = (GN + kBlock - 1) / kBlock;
-  __shared__ float xs[2][3][18][XS];
-  __shared__ float gs[2][16][GS];
+  using SV = typename std::conditional<V4, v4f, float>::type;
+  __shared__ __attribute__((aligned(16))) float xs[2][3][18][XS];
+  __shared__ __attribute__((aligned(16))) float gs[2][16][GS];
 
   const int mt = blockIdx.y % a.mtiles;
   const int nt = blockIdx.y / a.mtiles;
@@ -341,8 +347,10 @@ __global__ __launch_bounds__(kBlock) void k_conv_wgrad3(const WgradArgs a) {
   const bool active = wave < G::WM * G::WN;
   const int kq = lane >> 4;
 
-  // a chunk's values in registers: input patch, then output gradient
-  float xr[XR], gr[GR];
+  // a chunk's values in registers: input patch, then output gradient (VW
+  // channels per value)
+  constexpr int TMV = TM / VW, NTV = NT / VW;
+  SV xr[XR], gr[GR];
   auto fetch = [&](int p0) {
     const int w0 = p0 % a.W;   // the chunk's row: image b, row h, columns w0 .. w0 + 15
     const int bh = p0 / a.W;
@@ -350,20 +358,20 @@ __global__ __launch_bounds__(kBlock) void k_conv_wgrad3(const WgradArgs a) {
 #pragma unroll
     for (int k = 0; k < XR; ++k) {
       const int e = threadIdx.x + k * kBlock;
-      const int m = e % TM, pc = (e / TM) % 18, pr = e / (18 * TM);
-      const int hs = h + pr - 1, ws = w0 + pc - 1, ci = m0 + m;
-      float v = 0.f;
+      const int m = e % TMV, pc = (e / TMV) % 18, pr = e / (18 * TMV);
+      const int hs = h + pr - 1, ws = w0 + pc - 1, ci = m0 + VW * m;
+      SV v = SV{};
       if (e < XN && hs >= 0 && hs < a.H && ws >= 0 && ws < a.W && ci < a.cin)
-        v = a.x[((size_t)(bh + pr - 1) * a.W + ws) * a.cin + ci];
+        v = *(const SV*)(a.x + ((size_t)(bh + pr - 1) * a.W + ws) * a.cin + ci);
       xr[k] = v;
     }
 #pragma unroll
     for (int k = 0; k < GR; ++k) {
       const int e = threadIdx.x + k * kBlock;
-      const int n = e % NT, j = e / NT;
-      const int co = n0 + n;
-      float v = 0.f;
-      if (e < GN && p0 + j < p_end && co < a.cout) v = a.dy[((size_t)p0 + j) * a.cout + co];
+      const int n = e % NTV, j = e / NTV;
+      const int co = n0 + VW * n;
+      SV v = SV{};
+      if (e < GN && p0 + j < p_end && co < a.cout) v = *(const SV*)(a.dy + ((size_t)p0 + j) * a.cout + co);
       gr[k] = v;
     }
   };
@@ -371,12 +379,12 @@ __global__ __launch_bounds__(kBlock) void k_conv_wgrad3(const WgradArgs a) {
 #pragma unroll
     for (int k = 0; k < XR; ++k) {
       const int e = threadIdx.x + k * kBlock;
-      if (e < XN) xs[b][e / (18 * TM)][(e / TM) % 18][e % TM] = xr[k];
+      if (e < XN) *(SV*)&xs[b][e / (18 * TMV)][(e / TMV) % 18][VW * (e % TMV)] = xr[k];
     }
 #pragma unroll
     for (int k = 0; k < GR; ++k) {
       const int e = threadIdx.x + k * kBlock;
-      if (e < GN) gs[b][e / NT][e % NT] = gr[k];
+      if (e < GN) *(SV*)&gs[b][e / NTV][VW * (e % NTV)] = gr[k];
     }
   };
 
