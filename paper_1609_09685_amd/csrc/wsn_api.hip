@@ -630,4 +630,39 @@ lbm_status wsn_nhwc_to_fields(const float* y, const float* shift, const float* s
   return ok();
 }
 
+lbm_status wsn_mirror(const void* in, int32_t elem_bytes, int32_t batch, int32_t height,
+                      int32_t width, int32_t channels, int32_t flip_h, int32_t flip_w,
+                      const float* sign, void* out, void* stream) {
+  lbm_status s = check_image(batch, height, width, channels, "wsn_mirror");
+  if (s != LBM_OK) return s;
+  if (!in || !out) return fail(LBM_EINVAL, "wsn_mirror: NULL buffer");
+  if (in == out) return fail(LBM_EINVAL, "wsn_mirror: in and out must not overlap");
+  if (elem_bytes != 1 && elem_bytes != 4)
+    return fail(LBM_EINVAL, "wsn_mirror: elem_bytes must be 1 or 4, got %d", elem_bytes);
+  if ((flip_h != 0 && flip_h != 1) || (flip_w != 0 && flip_w != 1))
+    return fail(LBM_EINVAL, "wsn_mirror: flip_h and flip_w must be 0 or 1");
+  if (sign && (elem_bytes != 4 || channels > kMirrorC))
+    return fail(LBM_EINVAL, "wsn_mirror: sign needs float elements and at most %d channels",
+                kMirrorC);
+  if ((int64_t)batch * height * width >= (1ll << 31))
+    return fail(LBM_EINVAL, "wsn_mirror: more than 2^31 pixels");
+  MirrorSigns sg{};
+  if (sign)
+    for (int k = 0; k < channels; ++k) sg.s[k] = sign[k];
+  const size_t n = (size_t)batch * height * width;
+  hipStream_t st = (hipStream_t)stream;
+  if (elem_bytes == 1)
+    k_mirror<uint8_t, false><<<blocks_for(n), kBlock, 0, st>>>(
+        (const uint8_t*)in, height, width, channels, flip_h, flip_w, sg, n, (uint8_t*)out);
+  else if (sign)
+    k_mirror<float, true><<<blocks_for(n), kBlock, 0, st>>>(
+        (const float*)in, height, width, channels, flip_h, flip_w, sg, n, (float*)out);
+  else
+    k_mirror<float, false><<<blocks_for(n), kBlock, 0, st>>>(
+        (const float*)in, height, width, channels, flip_h, flip_w, sg, n, (float*)out);
+  HIP_TRY(hipGetLastError());
+  return ok();
+}
+
+
 }  // extern "C"

@@ -776,4 +776,32 @@ __global__ __launch_bounds__(kBlock) void k_nhwc_to_fields(const float* __restri
   if (!finite) bad[b] = 1;   // plain store of a flag; every writer stores the same value
 }
 
+// Per-channel factors of a mirror image (up to kMirrorC channels).
+constexpr int kMirrorC = 8;
+struct MirrorSigns {
+  float s[kMirrorC];
+};
+
+// Mirror image of NHWC images [b][h][w][c]: out pixel (b, h, w) is in pixel
+// (b, fh ? H - 1 - h : h, fw ? W - 1 - w : w); with SIGN, channel k is
+// multiplied by sg.s[k].
+template <class E, bool SIGN>
+__global__ __launch_bounds__(kBlock) void k_mirror(const E* __restrict__ in, int height, int width,
+                                                   int c, int fh, int fw, MirrorSigns sg,
+                                                   size_t npix, E* __restrict__ out) {
+  const size_t p = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (p >= npix) return;
+  const size_t hw = (size_t)height * width;
+  const size_t b = p / hw;
+  const int q = (int)(p - b * hw);
+  const int h = q / width, w = q - h * width;
+  const int hs = fh ? height - 1 - h : h, ws = fw ? width - 1 - w : w;
+  const E* src = in + (b * hw + (size_t)hs * width + ws) * c;
+  E* dst = out + p * c;
+  for (int k = 0; k < c; ++k) {
+    if constexpr (SIGN) dst[k] = src[k] * sg.s[k < kMirrorC ? k : 0];
+    else dst[k] = src[k];
+  }
+}
+
 }  // namespace wsn

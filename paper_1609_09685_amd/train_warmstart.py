@@ -7,7 +7,8 @@ it gives (zero vs linear-density vs learned), all on one GPU.
 Training samples use seeds 10000 + j, held-out samples 20000 + j (porosity
 U[0.6, 0.9], tau U[0.51, 1.0], 256 x 128 QSGS masks).  The parameters, the
 velocity scale and the measurements are written to --out (NumPy .npz, no
-pickles) and --report (JSON).
+pickles) and --report (JSON).  --augment adds the three mirror images of every
+training state (``warmstart.MIRRORS``).
 """
 import argparse
 import json
@@ -36,6 +37,8 @@ def main(argv=None):
     ap.add_argument("--max-steps", type=int, default=200000)
     ap.add_argument("--eval-max-steps", type=int, default=600000)
     ap.add_argument("--chunk", type=int, default=1024, help="samples per data-generation batch")
+    ap.add_argument("--augment", action="store_true",
+                    help="train on the data and its three mirror images (symmetries of the setup)")
     ap.add_argument("--out", default=None)
     ap.add_argument("--report", default=None)
     args = ap.parse_args(argv)
@@ -58,11 +61,12 @@ def main(argv=None):
     rep["u_scale"], rep["rho_scale"] = scales
     net = ws.new_network(args.batch, seed=0)
     t0 = time.perf_counter()
-    hist = ws.train(net, data, scales, epochs=args.epochs, lr=args.lr, lr_end=args.lr_end, log=log)
+    hist = ws.train(net, data, scales, epochs=args.epochs, lr=args.lr, lr_end=args.lr_end, log=log,
+                    augment=args.augment)
     torch.cuda.synchronize()
     rep["train_seconds"] = time.perf_counter() - t0
     rep["loss_per_epoch"] = hist
-    iters = args.epochs * (len(data) // args.batch)
+    iters = args.epochs * ((4 if args.augment else 1) * len(data) // args.batch)
     rep["train_iterations"] = iters
     rep["ms_per_iteration"] = 1e3 * rep["train_seconds"] / max(iters, 1)
     log(f"training: {iters} iterations in {rep['train_seconds']:.1f} s "

@@ -195,14 +195,41 @@ def new_network(batch, seed=0, levels=4, base=32):
                             base=base, height=NY, width=NX)
 
 
-def train(net, data, scales, epochs=20, lr=1e-3, lr_end=1e-5, seed=0, log=None):
+# Symmetries of the setup (Fig. 1) as (flip_h, flip_w) and the factors of the
+# targets (rho', u'_x, u'_y): the symmetric top and bottom planes make the
+# y-mirror of a steady state the steady state of the y-mirrored mask (u_y
+# changes sign); Stokes linearity makes the x-mirror with the pressure drop
+# reversed that of the x-mirrored mask (rho' and u_y change sign: the linear
+# drop between the ghost planes is odd about the middle, and mirror and
+# reversal each turn u_x round).
+MIRRORS = (((1, 0), (1.0, 1.0, -1.0)),
+           ((0, 1), (-1.0, 1.0, -1.0)),
+           ((1, 1), (-1.0, 1.0, 1.0)))
+
+
+def augmented(data, y):
+    """Inputs, targets and masks of the data followed by those of its three
+    mirror images (MIRRORS): 4 n training samples from n solved ones."""
+    import torch
+    xs, ys, ss = [data.x], [y], [data.solid]
+    for (fh, fw), sign in MIRRORS:
+        xs.append(wsn.mirror(data.x, fh, fw))
+        ys.append(wsn.mirror(y, fh, fw, sign))
+        ss.append(wsn.mirror(data.solid, fh, fw))
+    return torch.cat(xs), torch.cat(ys), torch.cat(ss)
+
+
+def train(net, data, scales, epochs=20, lr=1e-3, lr_end=1e-5, seed=0, log=None, augment=False):
     """Adam on the masked MSE; minibatches are contiguous slices of the data in a
     shuffled order per epoch, learning rate decayed geometrically to lr_end.
+    augment: train on the data and its three mirror images (``augmented``).
     Returns the mean loss of every epoch."""
     import torch
     B = net.batch
-    y_all = data.targets(scales)
-    nb = len(data) // B
+    x_all, y_all, s_all = data.x, data.targets(scales), data.solid
+    if augment:
+        x_all, y_all, s_all = augmented(data, y_all)
+    nb = len(x_all) // B
     rng = np.random.default_rng(seed)
     total = epochs * nb
     hist = []
@@ -212,7 +239,7 @@ def train(net, data, scales, epochs=20, lr=1e-3, lr_end=1e-5, seed=0, log=None):
         for i in rng.permutation(nb):
             sl = slice(i * B, (i + 1) * B)
             rate = lr * (lr_end / lr) ** (it / max(total - 1, 1))
-            losses.append(net.train_step(data.x[sl], y_all[sl], data.solid[sl], rate))
+            losses.append(net.train_step(x_all[sl], y_all[sl], s_all[sl], rate))
             it += 1
         ep_loss = float(torch.stack(losses).mean().item())
         hist.append(ep_loss)

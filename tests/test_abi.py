@@ -226,6 +226,16 @@ def test_wsn_sizes_and_validation():
     assert L.wsn_adam(fake, fake, fake, fake, 10, 1e-3, 0.9, 0.999, 1e-8, 0, None) == lbm.LBM_EINVAL
     assert L.wsn_adam(fake, fake, fake, fake, 10, 1e-3, 1.0, 0.999, 1e-8, 1, None) == lbm.LBM_EINVAL
     assert L.wsn_mse_work(0, ctypes.byref(n)) == lbm.LBM_EINVAL
+    sg = (ctypes.c_float * 9)(*([1.0] * 9))
+    other = fake + 4096
+    for args in [(fake, 2, 1, 4, 4, 3, 1, 0, None, other),      # element size
+                 (fake, 4, 1, 4, 4, 3, 2, 0, None, other),      # flip flag
+                 (fake, 1, 1, 4, 4, 1, 1, 0, sg, other),        # sign on bytes
+                 (fake, 4, 1, 4, 4, 9, 1, 0, sg, other),        # sign beyond 8 channels
+                 (fake, 4, 1, 4, 4, 3, 1, 1, None, fake),       # in place
+                 (None, 4, 1, 4, 4, 3, 1, 1, None, other),
+                 (fake, 4, 0, 4, 4, 3, 1, 1, None, other)]:
+        assert L.wsn_mirror(*args, None) == lbm.LBM_EINVAL, args
 
 
 def test_probe_rejects_bad_arguments():

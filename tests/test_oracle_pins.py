@@ -375,6 +375,35 @@ def test_mirror_and_reversal_symmetry(small_mask):
     assert abs(kx - k) / k < 1e-6
 
 
+def _normalised_fields(mask, rin=1.0005, rout=0.9995):
+    """Steady (rho - rho_lin) / drho, u_x, u_y of the oracle, NaN on solids."""
+    o = oracle.Oracle(9, mask, 0.8, rin, rout)
+    ok, _, _ = o.run_to_steady(1e-12, 100, 400000)
+    assert ok
+    rho, u = o.macro()
+    nx = mask.shape[1]
+    lin = rin + (rout - rin) * (np.arange(nx) + 1) / (nx + 1)
+    return np.stack([(rho[0] - lin) / (rin - rout), u[0, ..., 0], u[0, ..., 1]], -1)
+
+
+def test_mirror_table_of_the_training_data(small_mask):
+    """The steady fields of a mirrored mask are the mirrored fields times the
+    factors the warm start's training augmentation uses: exactly for the
+    y-mirror (symmetric planes), to O(drho) for the x-mirror (Stokes
+    linearity: it reverses the flow, which the pressure drop then restores)."""
+    from paper_1609_09685_amd.warmstart import MIRRORS
+    f0 = _normalised_fields(small_mask)
+    scale = np.nanmax(np.abs(f0), axis=(0, 1))
+    assert len(MIRRORS) == 3
+    for (fh, fw), sign in MIRRORS:
+        m = small_mask[::-1] if fh else small_mask
+        m = np.ascontiguousarray(m[:, ::-1] if fw else m)
+        want = f0[::-1] if fh else f0
+        want = (want[:, ::-1] if fw else want) * np.asarray(sign)
+        err = np.nanmax(np.abs(_normalised_fields(m) - want), axis=(0, 1)) / scale
+        assert (err < (1e-8 if not fw else 3e-3)).all(), ((fh, fw), err)
+
+
 def test_start_independence(small_mask):
     """The converged k is the fixed point of the map, whichever rest start."""
     k_u, _, s_u = _k(small_mask, start="uniform", tol=1e-12)
