@@ -3,7 +3,7 @@
 the HIP kernels, and the start it gives against the zero and linear starts.
 
 Reduced budget (4096 training samples, 20 epochs, 96 held-out samples) so
-that the module runs in about three minutes; the full-size figures come from
+that the module runs in about a minute and a half; the full-size figures come from
 ``python -m paper_1609_09685_amd.train_warmstart``.  Everything is seeded and
 the kernels are deterministic, so the figures repeat exactly.
 
