@@ -157,18 +157,19 @@ lbm_status wsn_nhwc_to_fields(const float *y, const float *shift, const float *s
 
 /* Mirror image of a batch of NHWC images in[batch][height][width][channels]
  * (elem_bytes 4: float32; 1: uint8) into out (same shape; must not overlap
- * in): out[b][h][w][c] = sign[c] * in[b][h'][w'][c] with h' = height - 1 - h
- * if flip_h else h, and w' likewise with flip_w.  sign: host array of
- * `channels` (<= 8) factors, float images only, or NULL for a plain copy of
- * the mirrored pixels.  Used to augment the warm start's training data with
- * the symmetries of the paper's setup (Fig. 1): the symmetric top and bottom
- * boundaries make a steady state mirrored in y a steady state of the mirrored
- * mask (u_y changes sign), and Stokes linearity makes one mirrored in x, with
- * the pressure drop reversed, the steady state of the x-mirrored mask (the
- * deviation from the linear density drop and u_y change sign). */
+ * in): out[b][h][w][c] = scale[c] * in[b][h'][w'][c] (+ out[b][h][w][c] if
+ * accumulate) with h' = height - 1 - h if flip_h else h, and w' likewise with
+ * flip_w.  scale: host array of `channels` (<= 8) factors, or NULL for 1;
+ * scale and accumulate need float images.  For the warm start's training
+ * data and predictions: by the symmetries of the paper's setup (Fig. 1) the
+ * symmetric top and bottom boundaries make a steady state mirrored in y a
+ * steady state of the mirrored mask (u_y changes sign), and Stokes linearity
+ * makes one mirrored in x, with the pressure drop reversed, the steady state
+ * of the x-mirrored mask (the deviation from the linear density drop and u_y
+ * change sign). */
 lbm_status wsn_mirror(const void *in, int32_t elem_bytes, int32_t batch, int32_t height,
                       int32_t width, int32_t channels, int32_t flip_h, int32_t flip_w,
-                      const float *sign, void *out, void *stream);
+                      const float *scale, int32_t accumulate, void *out, void *stream);
 
 #ifdef __cplusplus
 }

@@ -632,34 +632,46 @@ lbm_status wsn_nhwc_to_fields(const float* y, const float* shift, const float* s
 
 lbm_status wsn_mirror(const void* in, int32_t elem_bytes, int32_t batch, int32_t height,
                       int32_t width, int32_t channels, int32_t flip_h, int32_t flip_w,
-                      const float* sign, void* out, void* stream) {
+                      const float* scale, int32_t accumulate, void* out, void* stream) {
   lbm_status s = check_image(batch, height, width, channels, "wsn_mirror");
   if (s != LBM_OK) return s;
   if (!in || !out) return fail(LBM_EINVAL, "wsn_mirror: NULL buffer");
   if (in == out) return fail(LBM_EINVAL, "wsn_mirror: in and out must not overlap");
   if (elem_bytes != 1 && elem_bytes != 4)
     return fail(LBM_EINVAL, "wsn_mirror: elem_bytes must be 1 or 4, got %d", elem_bytes);
-  if ((flip_h != 0 && flip_h != 1) || (flip_w != 0 && flip_w != 1))
-    return fail(LBM_EINVAL, "wsn_mirror: flip_h and flip_w must be 0 or 1");
-  if (sign && (elem_bytes != 4 || channels > kMirrorC))
-    return fail(LBM_EINVAL, "wsn_mirror: sign needs float elements and at most %d channels",
-                kMirrorC);
+  if ((flip_h != 0 && flip_h != 1) || (flip_w != 0 && flip_w != 1) ||
+      (accumulate != 0 && accumulate != 1))
+    return fail(LBM_EINVAL, "wsn_mirror: flip_h, flip_w and accumulate must be 0 or 1");
+  if ((scale || accumulate) && elem_bytes != 4)
+    return fail(LBM_EINVAL, "wsn_mirror: scale and accumulate need float elements");
+  if (scale && channels > kMirrorC)
+    return fail(LBM_EINVAL, "wsn_mirror: scale covers at most %d channels", kMirrorC);
   if ((int64_t)batch * height * width >= (1ll << 31))
     return fail(LBM_EINVAL, "wsn_mirror: more than 2^31 pixels");
-  MirrorSigns sg{};
-  if (sign)
-    for (int k = 0; k < channels; ++k) sg.s[k] = sign[k];
+  MirrorScale sc{};
+  if (scale)
+    for (int k = 0; k < channels; ++k) sc.s[k] = scale[k];
   const size_t n = (size_t)batch * height * width;
+  const unsigned g = blocks_for(n);
   hipStream_t st = (hipStream_t)stream;
+  const float* fi = (const float*)in;
+  float* fo = (float*)out;
   if (elem_bytes == 1)
-    k_mirror<uint8_t, false><<<blocks_for(n), kBlock, 0, st>>>(
-        (const uint8_t*)in, height, width, channels, flip_h, flip_w, sg, n, (uint8_t*)out);
-  else if (sign)
-    k_mirror<float, true><<<blocks_for(n), kBlock, 0, st>>>(
-        (const float*)in, height, width, channels, flip_h, flip_w, sg, n, (float*)out);
+    k_mirror<uint8_t, false, false><<<g, kBlock, 0, st>>>((const uint8_t*)in, height, width,
+                                                          channels, flip_h, flip_w, sc, n,
+                                                          (uint8_t*)out);
+  else if (scale && accumulate)
+    k_mirror<float, true, true><<<g, kBlock, 0, st>>>(fi, height, width, channels, flip_h, flip_w,
+                                                      sc, n, fo);
+  else if (scale)
+    k_mirror<float, true, false><<<g, kBlock, 0, st>>>(fi, height, width, channels, flip_h,
+                                                       flip_w, sc, n, fo);
+  else if (accumulate)
+    k_mirror<float, false, true><<<g, kBlock, 0, st>>>(fi, height, width, channels, flip_h,
+                                                       flip_w, sc, n, fo);
   else
-    k_mirror<float, false><<<blocks_for(n), kBlock, 0, st>>>(
-        (const float*)in, height, width, channels, flip_h, flip_w, sg, n, (float*)out);
+    k_mirror<float, false, false><<<g, kBlock, 0, st>>>(fi, height, width, channels, flip_h,
+                                                        flip_w, sc, n, fo);
   HIP_TRY(hipGetLastError());
   return ok();
 }

@@ -778,16 +778,16 @@ __global__ __launch_bounds__(kBlock) void k_nhwc_to_fields(const float* __restri
 
 // Per-channel factors of a mirror image (up to kMirrorC channels).
 constexpr int kMirrorC = 8;
-struct MirrorSigns {
+struct MirrorScale {
   float s[kMirrorC];
 };
 
 // Mirror image of NHWC images [b][h][w][c]: out pixel (b, h, w) is in pixel
-// (b, fh ? H - 1 - h : h, fw ? W - 1 - w : w); with SIGN, channel k is
-// multiplied by sg.s[k].
-template <class E, bool SIGN>
+// (b, fh ? H - 1 - h : h, fw ? W - 1 - w : w); with SCALE, channel k is
+// multiplied by sc.s[k]; with ACC, the result is added to out.
+template <class E, bool SCALE, bool ACC>
 __global__ __launch_bounds__(kBlock) void k_mirror(const E* __restrict__ in, int height, int width,
-                                                   int c, int fh, int fw, MirrorSigns sg,
+                                                   int c, int fh, int fw, MirrorScale sc,
                                                    size_t npix, E* __restrict__ out) {
   const size_t p = (size_t)blockIdx.x * kBlock + threadIdx.x;
   if (p >= npix) return;
@@ -799,8 +799,10 @@ __global__ __launch_bounds__(kBlock) void k_mirror(const E* __restrict__ in, int
   const E* src = in + (b * hw + (size_t)hs * width + ws) * c;
   E* dst = out + p * c;
   for (int k = 0; k < c; ++k) {
-    if constexpr (SIGN) dst[k] = src[k] * sg.s[k < kMirrorC ? k : 0];
-    else dst[k] = src[k];
+    E v = src[k];
+    if constexpr (SCALE) v = v * sc.s[k < kMirrorC ? k : 0];
+    if constexpr (ACC) v = dst[k] + v;
+    dst[k] = v;
   }
 }
 

@@ -8,7 +8,8 @@ Training samples use seeds 10000 + j, held-out samples 20000 + j (porosity
 U[0.6, 0.9], tau U[0.51, 1.0], 256 x 128 QSGS masks).  The parameters, the
 velocity scale and the measurements are written to --out (NumPy .npz, no
 pickles) and --report (JSON).  --augment adds the three mirror images of every
-training state (``warmstart.MIRRORS``).
+training state (``warmstart.MIRRORS``); --tta averages the learned start's
+predictions over the mask's mirror images.
 """
 import argparse
 import json
@@ -39,6 +40,8 @@ def main(argv=None):
     ap.add_argument("--chunk", type=int, default=1024, help="samples per data-generation batch")
     ap.add_argument("--augment", action="store_true",
                     help="train on the data and its three mirror images (symmetries of the setup)")
+    ap.add_argument("--tta", action="store_true",
+                    help="learned start: average the predictions of the mask's mirror images")
     ap.add_argument("--out", default=None)
     ap.add_argument("--report", default=None)
     args = ap.parse_args(argv)
@@ -74,7 +77,7 @@ def main(argv=None):
     del data
     torch.cuda.empty_cache()
     ev = ws.evaluate(net, range(20000, 20000 + args.test), scales, max_steps=args.eval_max_steps,
-                     precision=args.eval_precision, log=log)
+                     precision=args.eval_precision, log=log, tta=args.tta)
     rep["eval"] = ev
     summary = {}
     for name in ("zero", "linear", "learned"):

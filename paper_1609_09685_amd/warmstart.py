@@ -248,12 +248,14 @@ def train(net, data, scales, epochs=20, lr=1e-3, lr_end=1e-5, seed=0, log=None, 
     return hist
 
 
-def predict(net, masks, taus, scales):
+def predict(net, masks, taus, scales, tta=False):
     """Fields (rho [B,H,W], u [B,2,H,W]) and the non-finite flags of the network's
     prediction for the samples (any number; run in chunks of the net's batch).
-    The velocity is set to zero in fluid pockets that no path along lattice
-    links joins to the inlet or outlet: the steady flow there is exactly zero,
-    and a closed pocket keeps whatever momentum it starts with."""
+    tta: average the predictions for the mask and its three mirror images
+    (MIRRORS), each mirrored back.  The velocity is set to zero in fluid
+    pockets that no path along lattice links joins to the inlet or outlet: the
+    steady flow there is exactly zero, and a closed pocket keeps whatever
+    momentum it starts with."""
     import torch
     from .qsgs import open_fluid
     n = len(masks)
@@ -267,6 +269,12 @@ def predict(net, masks, taus, scales):
         keep = _dev(np.stack([open_fluid(mk) for mk in masks[c0:c0 + m]]))
         x = wsn.pack_input(solid, _dev(features(taus[c0:c0 + m], NX)))
         y = net.infer(x)
+        if tta:
+            w = 1.0 / (1 + len(MIRRORS))
+            y = wsn.mirror(y, 0, 0, (w, w, w))
+            for (fh, fw), sign in MIRRORS:
+                wsn.mirror(net.infer(wsn.mirror(x, fh, fw)), fh, fw, [w * v for v in sign],
+                           out=y, accumulate=True)
         wsn.nhwc_to_fields(y, _dev(shift[c0:c0 + m]), _dev(inv[c0:c0 + m]),
                            slope=_dev(slope[c0:c0 + m]), keep_u=keep,
                            out=(rho[c0:c0 + m], u[c0:c0 + m], bad[c0:c0 + m]))
@@ -377,13 +385,15 @@ def step_seconds(mask, tau, precision, steps=2000):
     return e0.elapsed_time(e1) / 1e3 / steps
 
 
-def evaluate(net, seeds, scales, tol=1e-9, max_steps=600000, precision="fp64", log=None):
+def evaluate(net, seeds, scales, tol=1e-9, max_steps=600000, precision="fp64", log=None,
+             tta=False):
     """Zero, linear-density and learned starts on the samples `seeds`: per-sample
     steps and permeabilities, the wall time of each batch job (the learned
     start's includes inference, the field conversion and lbm_set_macro), and
     per sample the time until its permeability stays within K_TOL of the
     converged value, as if it ran alone: its steps to that point times the
-    step time of one sample alone, plus its share of the start's own work."""
+    step time of one sample alone, plus its share of the start's own work.
+    tta: the learned start averages the predictions of the mirror images."""
     smp = [sample(s) for s in seeds]
     masks = [m for m, _, _ in smp]
     taus = [t for _, t, _ in smp]
@@ -408,7 +418,7 @@ def evaluate(net, seeds, scales, tol=1e-9, max_steps=600000, precision="fp64", l
         ref["rho"], ref["u"] = rho, u
 
     def learned(b):
-        rho, u, bad = predict(net, masks, taus, scales)
+        rho, u, bad = predict(net, masks, taus, scales, tta=tta)
         info["pred"] = (rho.cpu().numpy(), u.cpu().numpy())
         badh = bad.cpu().numpy()
         for j, s in enumerate(b.solvers):

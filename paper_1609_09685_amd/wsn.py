@@ -45,7 +45,8 @@ _SIGS = {
     "wsn_pack_input": (_c.c_int, [_p, _p, _i, _i, _i, _p, _p]),
     "wsn_fields_to_nhwc": (_c.c_int, [_p, _p, _p, _p, _p, _i, _i, _i, _p, _p]),
     "wsn_nhwc_to_fields": (_c.c_int, [_p, _p, _p, _p, _p, _i, _i, _i, _p, _p, _p, _p]),
-    "wsn_mirror": (_c.c_int, [_p, _i, _i, _i, _i, _i, _i, _i, _c.POINTER(_c.c_float), _p, _p]),
+    "wsn_mirror": (_c.c_int, [_p, _i, _i, _i, _i, _i, _i, _i, _c.POINTER(_c.c_float), _i, _p,
+                              _p]),
 }
 
 _lib = None
@@ -233,10 +234,11 @@ def nhwc_to_fields(y, shift, scale, slope=None, keep_u=None, out=None):
     return rho, u, bad
 
 
-def mirror(t, flip_h, flip_w, sign=None, out=None):
+def mirror(t, flip_h, flip_w, scale=None, out=None, accumulate=False):
     """Mirror image of t (uint8 [B,H,W] or float32 [B,H,W] / [B,H,W,C]) along H
-    (flip_h) and / or W (flip_w), channel k multiplied by sign[k] (float only);
-    into `out` if given (same shape and type, not overlapping t)."""
+    (flip_h) and / or W (flip_w), channel k multiplied by scale[k] (float only);
+    into `out` if given (same shape and type, not overlapping t), added to it
+    with accumulate (float only)."""
     import torch
     if not t.is_cuda or not t.is_contiguous() or t.dtype not in (torch.uint8, torch.float32):
         raise ValueError("expected a contiguous uint8 or float32 device tensor")
@@ -244,16 +246,19 @@ def mirror(t, flip_h, flip_w, sign=None, out=None):
         raise ValueError("expected [B,H,W] or [B,H,W,C]")
     B, H, W = t.shape[:3]
     C = t.shape[3] if t.dim() == 4 else 1
+    if accumulate and out is None:
+        raise ValueError("accumulate needs out")
     o = out if out is not None else torch.empty_like(t)
     if o.shape != t.shape or o.dtype != t.dtype or not o.is_contiguous():
         raise ValueError("out has the wrong shape or type")
-    sg = None
-    if sign is not None:
-        if len(sign) != C:
-            raise ValueError("sign needs one factor per channel")
-        sg = (ctypes.c_float * C)(*[float(v) for v in sign])
+    sc = None
+    if scale is not None:
+        if len(scale) != C:
+            raise ValueError("scale needs one factor per channel")
+        sc = (ctypes.c_float * C)(*[float(v) for v in scale])
     _check(lib().wsn_mirror(_ptr(t), t.element_size(), B, H, W, C, int(bool(flip_h)),
-                            int(bool(flip_w)), sg, _ptr(o), _stream(t.device)))
+                            int(bool(flip_w)), sc, int(bool(accumulate)), _ptr(o),
+                            _stream(t.device)))
     return o
 
 

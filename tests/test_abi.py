@@ -228,13 +228,15 @@ def test_wsn_sizes_and_validation():
     assert L.wsn_mse_work(0, ctypes.byref(n)) == lbm.LBM_EINVAL
     sg = (ctypes.c_float * 9)(*([1.0] * 9))
     other = fake + 4096
-    for args in [(fake, 2, 1, 4, 4, 3, 1, 0, None, other),      # element size
-                 (fake, 4, 1, 4, 4, 3, 2, 0, None, other),      # flip flag
-                 (fake, 1, 1, 4, 4, 1, 1, 0, sg, other),        # sign on bytes
-                 (fake, 4, 1, 4, 4, 9, 1, 0, sg, other),        # sign beyond 8 channels
-                 (fake, 4, 1, 4, 4, 3, 1, 1, None, fake),       # in place
-                 (None, 4, 1, 4, 4, 3, 1, 1, None, other),
-                 (fake, 4, 0, 4, 4, 3, 1, 1, None, other)]:
+    for args in [(fake, 2, 1, 4, 4, 3, 1, 0, None, 0, other),      # element size
+                 (fake, 4, 1, 4, 4, 3, 2, 0, None, 0, other),      # flip flag
+                 (fake, 4, 1, 4, 4, 3, 1, 0, None, 2, other),      # accumulate flag
+                 (fake, 1, 1, 4, 4, 1, 1, 0, sg, 0, other),        # scale on bytes
+                 (fake, 1, 1, 4, 4, 1, 1, 0, None, 1, other),      # accumulate on bytes
+                 (fake, 4, 1, 4, 4, 9, 1, 0, sg, 0, other),        # scale beyond 8 channels
+                 (fake, 4, 1, 4, 4, 3, 1, 1, None, 0, fake),       # in place
+                 (None, 4, 1, 4, 4, 3, 1, 1, None, 0, other),
+                 (fake, 4, 0, 4, 4, 3, 1, 1, None, 0, other)]:
         assert L.wsn_mirror(*args, None) == lbm.LBM_EINVAL, args
 
 

@@ -298,22 +298,29 @@ def test_field_conversions():
 
 @pytest.mark.parametrize("fh,fw", [(0, 0), (1, 0), (0, 1), (1, 1)])
 def test_mirror(fh, fw):
-    """Mirror images of float NHWC images (with per-channel signs, and without)
-    and of uint8 masks, bitwise against NumPy's flips, on odd sizes that leave
-    a ragged last block."""
-    def ref(a, sign=None):
+    """Mirror images of float NHWC images (with per-channel factors, and
+    without, and added to an output) and of uint8 masks, against NumPy's flips
+    (bitwise where no arithmetic is done), on odd sizes that leave a ragged
+    last block."""
+    def ref(a, scale=None):
         r = a[:, ::-1] if fh else a
         r = r[:, :, ::-1] if fw else r
-        return r * np.asarray(sign, a.dtype) if sign is not None else r
+        return r * np.asarray(scale, a.dtype) if scale is not None else r
     y = RNG.standard_normal((3, 17, 29, 3)).astype(np.float32)
-    sign = (-1.0, 1.0, -1.0)
-    out = wsn.mirror(dev(y), fh, fw, sign).cpu().numpy()
-    assert np.array_equal(out, ref(y, sign))
+    scale = (-1.0, 0.25, -0.5)
+    out = wsn.mirror(dev(y), fh, fw, scale).cpu().numpy()
+    assert np.array_equal(out, ref(y, scale))
     x = RNG.standard_normal((2, 5, 7, 2)).astype(np.float32)
     assert np.array_equal(wsn.mirror(dev(x), fh, fw).cpu().numpy(), ref(x))
     m = (RNG.random((4, 9, 33)) < 0.4).astype(np.uint8)
     got = wsn.mirror(torch.tensor(m, device="cuda"), fh, fw).cpu().numpy()
     assert np.array_equal(got, ref(m))
     pre = torch.full((3, 17, 29, 3), 7.0, device="cuda")
-    assert wsn.mirror(dev(y), fh, fw, sign, out=pre) is pre
-    assert np.array_equal(pre.cpu().numpy(), ref(y, sign))
+    assert wsn.mirror(dev(y), fh, fw, scale, out=pre) is pre
+    assert np.array_equal(pre.cpu().numpy(), ref(y, scale))
+    acc = dev(y)
+    wsn.mirror(dev(y), fh, fw, scale, out=acc, accumulate=True)
+    assert np.array_equal(acc.cpu().numpy(), y + ref(y, scale))
+    acc = dev(x)
+    wsn.mirror(dev(x), fh, fw, out=acc, accumulate=True)
+    assert np.array_equal(acc.cpu().numpy(), x + ref(x))
