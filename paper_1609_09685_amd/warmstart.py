@@ -355,7 +355,9 @@ def run_checked(masks, taus, start, precision, tol, max_steps, rerun_failed=True
 def field_errors(pred_rho, pred_u, ref_rho, ref_u, solid, taus, scales):
     """RMS error of the prediction over fluid nodes in the network's units
     (the targets rho', u'), per channel, over all samples, with the RMS of the
-    reference targets."""
+    reference targets; and per sample the ratio of the predicted to the
+    reference sum of u_x over the fluid nodes (the start's flux against the
+    converged one)."""
     shift, slope, fwd, _ = target_maps(taus, NX, scales)
     xp = np.arange(1, NX + 1, dtype=np.float64)[None, None, :]
     fl = solid == 0
@@ -367,6 +369,12 @@ def field_errors(pred_rho, pred_u, ref_rho, ref_u, solid, taus, scales):
         ref = (r - base) * fwd[:, c][:, None, None]
         out[("rho", "ux", "uy")[c]] = dict(rms_err=float(np.sqrt((e[fl] ** 2).mean())),
                                            rms_ref=float(np.sqrt((ref[fl] ** 2).mean())))
+    ratio = (np.where(fl, pred_u[:, 0], 0.0).sum(axis=(1, 2)) /
+             np.where(fl, ref_u[:, 0], 0.0).sum(axis=(1, 2)))
+    out["ux_sum_ratio"] = dict(median=float(np.median(ratio)),
+                               p10=float(np.percentile(ratio, 10)),
+                               p90=float(np.percentile(ratio, 90)),
+                               per_sample=[float(v) for v in ratio])
     return out
 
 
@@ -457,7 +465,9 @@ def evaluate(net, seeds, scales, tol=1e-9, max_steps=600000, precision="fp64", l
                 f"to k within {K_TOL:g}: median {np.median(a):.0f} steps, "
                 f"{np.median(t) * 1e3:.1f} ms per sample alone (sum {t.sum():.2f} s); batch "
                 f"{out[name]['seconds']:.2f} s, reruns {out[name]['reruns']}")
-        log(f"prediction error (network units): {out['prediction_error']}")
+        pe = {k: ({kk: vv for kk, vv in v.items() if kk != "per_sample"}) for k, v in
+              out["prediction_error"].items()}
+        log(f"prediction error (network units): {pe}")
     return out
 
 
