@@ -324,3 +324,57 @@ def test_mirror(fh, fw):
     acc = dev(x)
     wsn.mirror(dev(x), fh, fw, out=acc, accumulate=True)
     assert np.array_equal(acc.cpu().numpy(), x + ref(x))
+
+
+def test_augmented_training_views():
+    """The mirrored training data: the samples, then their three mirror images
+    with the target factors of MIRRORS (masks and inputs unscaled), bitwise
+    against NumPy's flips."""
+    from paper_1609_09685_amd import warmstart as ws
+    n, H, W = 3, 8, 16
+    x = RNG.standard_normal((n, H, W, 2)).astype(np.float32)
+    y = RNG.standard_normal((n, H, W, 3)).astype(np.float32)
+    solid = (RNG.random((n, H, W)) < 0.3).astype(np.uint8)
+    data = ws.Dataset(dev(x), None, None, torch.tensor(solid, device="cuda"), [0.6] * n,
+                      [0] * n, [0.0] * n, [True] * n, list(range(n)))
+    xa, ya, sa = (t.cpu().numpy() for t in ws.augmented(data, dev(y)))
+    assert xa.shape == (4 * n, H, W, 2) and ya.shape == (4 * n, H, W, 3) and sa.shape == (4 * n, H, W)
+    views = [((0, 0), (1.0, 1.0, 1.0))] + list(ws.MIRRORS)
+    for v, ((fh, fw), sign) in enumerate(views):
+        def flip(a):
+            r = a[:, ::-1] if fh else a
+            return r[:, :, ::-1] if fw else r
+        blk = slice(v * n, (v + 1) * n)
+        assert np.array_equal(xa[blk], flip(x))
+        assert np.array_equal(sa[blk], flip(solid))
+        assert np.array_equal(ya[blk], flip(y) * np.asarray(sign, np.float32))
+
+
+@pytest.mark.parametrize("fh,fw", [(1, 0), (0, 1), (1, 1)])
+def test_averaged_prediction_is_mirror_equivariant(fh, fw):
+    """Averaged over the mirror images, the learned start of a mirrored mask is
+    the mirrored start of the mask (density deviation from the linear drop and
+    u_y with the factors of MIRRORS), for any weights: a flip or factor wrong
+    anywhere in the averaging breaks it."""
+    from paper_1609_09685_amd import warmstart as ws
+    net = ws.new_network(2, seed=3)
+    masks = [ws.sample(s)[0] for s in (20001, 20002)]
+    taus = [0.6, 0.85]
+    scales = (1.3, 0.2)
+
+    def flip(a):
+        r = a[..., ::-1, :] if fh else a
+        return r[..., ::-1] if fw else r
+
+    rho, u, bad = (t.cpu().numpy() for t in ws.predict(net, masks, taus, scales, tta=True))
+    mm = [np.ascontiguousarray(flip(m)) for m in masks]
+    rho2, u2, bad2 = (t.cpu().numpy() for t in ws.predict(net, mm, taus, scales, tta=True))
+    assert not bad.any() and not bad2.any()
+    lin = ws.RHO_IN + (ws.RHO_OUT - ws.RHO_IN) * (np.arange(ws.NX) + 1.0) / (ws.NX + 1)
+    sign = dict(ws.MIRRORS)[(fh, fw)]
+    drho = ws.RHO_IN - ws.RHO_OUT
+    want_dev = sign[0] * flip(rho.astype(np.float64) - lin)
+    assert np.abs((rho2 - lin) - want_dev).max() <= 1e-3 * drho
+    for c in range(2):
+        want = sign[1 + c] * flip(u[:, c])
+        assert np.abs(u2[:, c] - want).max() <= 1e-5 * np.abs(u[:, c]).max()
