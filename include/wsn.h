@@ -135,6 +135,24 @@ lbm_status wsn_upcat_backward(const float *gcat, float *gdeep, float *gskip, int
 lbm_status wsn_pack_input(const uint8_t *solid, const float *feat, int32_t batch, int32_t height,
                           int32_t width, float *x, void *stream);
 
+/* Resistance profile along x of each mask (solid: device uint8 [batch][height][width],
+ * 1 = solid; profile: device float [batch][width], width <= 16384): with phi(x)
+ * the fluid fraction of column x (at least 1/height) and the Kozeny-Carman
+ * resistance R(x) = (1 - phi + 1/height)^2 / phi^3, profile[b][x] =
+ * (x + 1)/(width + 1) - sum_{x' <= x} R(x') / sum_x' R(x'): how a density drop
+ * that concentrates in the resistive columns departs from the linear drop
+ * between the pressure ghost planes (the paper's inlet and outlet
+ * conditions), in units of the drop.  An optional network input that carries
+ * information along the whole length, which a convolution cannot see. */
+lbm_status wsn_column_profile(const uint8_t *solid, int32_t batch, int32_t height, int32_t width,
+                              float *profile, void *stream);
+
+/* Network input with the profile as a third channel: x[b][p][0..1] as
+ * wsn_pack_input, x[b][p][2] = scale * profile[b][column of p]. */
+lbm_status wsn_pack_input_profile(const uint8_t *solid, const float *feat, const float *profile,
+                                  float scale, int32_t batch, int32_t height, int32_t width,
+                                  float *x, void *stream);
+
 /* Solver fields of a batch (rho [batch][height][width] and u [batch][2][height][width],
  * the layout of lbm_get_macro per sample) into NHWC [batch][height][width][3]:
  * y_k = (f_k - shift[3 b + k] - slope[3 b + k] (x + 1)) * scale[3 b + k],

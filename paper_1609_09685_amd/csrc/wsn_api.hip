@@ -601,6 +601,32 @@ lbm_status wsn_pack_input(const uint8_t* solid, const float* feat, int32_t batch
   return ok();
 }
 
+lbm_status wsn_column_profile(const uint8_t* solid, int32_t batch, int32_t height, int32_t width,
+                              float* profile, void* stream) {
+  lbm_status s = check_image(batch, height, width, 1, "wsn_column_profile");
+  if (s != LBM_OK) return s;
+  if (!solid || !profile) return fail(LBM_EINVAL, "wsn_column_profile: NULL buffer");
+  if (width > 16384) return fail(LBM_EINVAL, "wsn_column_profile: width above 16384");
+  k_column_profile<<<(unsigned)batch, kBlock, (size_t)width * sizeof(float), (hipStream_t)stream>>>(
+      solid, height, width, profile);
+  HIP_TRY(hipGetLastError());
+  return ok();
+}
+
+lbm_status wsn_pack_input_profile(const uint8_t* solid, const float* feat, const float* profile,
+                                  float scale, int32_t batch, int32_t height, int32_t width,
+                                  float* x, void* stream) {
+  lbm_status s = check_image(batch, height, width, 3, "wsn_pack_input_profile");
+  if (s != LBM_OK) return s;
+  if (!solid || !feat || !profile || !x) return fail(LBM_EINVAL, "wsn_pack_input_profile: NULL buffer");
+  if (!isfinite(scale)) return fail(LBM_EINVAL, "wsn_pack_input_profile: scale not finite");
+  const size_t n = (size_t)batch * height * width;
+  k_pack_input_profile<<<blocks_for(n), kBlock, 0, (hipStream_t)stream>>>(solid, feat, profile, scale,
+                                                                           height * width, width, n, x);
+  HIP_TRY(hipGetLastError());
+  return ok();
+}
+
 lbm_status wsn_fields_to_nhwc(const float* rho, const float* u, const float* shift,
                               const float* slope, const float* scale, int32_t batch,
                               int32_t height, int32_t width, float* y, void* stream) {

@@ -722,6 +722,56 @@ __global__ __launch_bounds__(kBlock) void k_pack_input(const uint8_t* __restrict
   x[2 * p + 1] = feat[p / hw];
 }
 
+// Network input with a third channel: x[p][2] = scale * profile[b][column].
+__global__ __launch_bounds__(kBlock) void k_pack_input_profile(const uint8_t* __restrict__ solid,
+                                                               const float* __restrict__ feat,
+                                                               const float* __restrict__ profile,
+                                                               float scale, int hw, int width,
+                                                               size_t npix, float* __restrict__ x) {
+  const size_t p = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (p >= npix) return;
+  const size_t b = p / hw;
+  const int col = (int)(p % hw) % width;
+  x[3 * p] = (float)solid[p];
+  x[3 * p + 1] = feat[b];
+  x[3 * p + 2] = scale * profile[b * width + col];
+}
+
+// Resistance profile along x of each sample's mask (one block per sample,
+// `width` floats of dynamic LDS): the fluid fraction phi(x) of column x
+// (at least 1/H), a Kozeny-Carman resistance R(x) = (1 - phi + 1/H)^2 / phi^3,
+// its normalised running sum C(x) = sum_{x' <= x} R / sum R (summed in x
+// order), and profile[b][x] = (x + 1)/(W + 1) - C(x): where a density drop
+// concentrated in the resistive columns departs from the linear drop between
+// the ghost planes, in units of the drop.
+__global__ __launch_bounds__(kBlock) void k_column_profile(const uint8_t* __restrict__ solid,
+                                                           int height, int width,
+                                                           float* __restrict__ profile) {
+  extern __shared__ float run[];
+  const size_t b = blockIdx.x;
+  const uint8_t* s = solid + b * (size_t)height * width;
+  const float hmin = 1.0f / (float)height;
+  for (int x = threadIdx.x; x < width; x += kBlock) {
+    int fluid = 0;
+    for (int h = 0; h < height; ++h) fluid += s[(size_t)h * width + x] == 0;
+    const float phi = fmaxf((float)fluid * hmin, hmin);
+    const float a = 1.0f - phi + hmin;
+    run[x] = a * a / (phi * phi * phi);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float acc = 0.f;
+    for (int x = 0; x < width; ++x) {
+      acc += run[x];
+      run[x] = acc;
+    }
+  }
+  __syncthreads();
+  const float total = run[width - 1];
+  for (int x = threadIdx.x; x < width; x += kBlock)
+    profile[b * width + x] = (float)(x + 1) / (float)(width + 1) - run[x] / total;
+}
+
 // Solver fields (rho [b][p], u [b][2][p]) -> NHWC [b][p][3]:
 // y_k = (f_k - shift[3b + k] - slope[3b + k] (x + 1)) * scale[3b + k], with x
 // the pixel's column (slope may be null: 0).  A slope along x lets the

@@ -9,7 +9,8 @@ U[0.6, 0.9], tau U[0.51, 1.0], 256 x 128 QSGS masks).  The parameters, the
 velocity scale and the measurements are written to --out (NumPy .npz, no
 pickles) and --report (JSON).  --augment adds the three mirror images of every
 training state (``warmstart.MIRRORS``); --tta averages the learned start's
-predictions over the mask's mirror images.
+predictions over the mask's mirror images; --profile gives the network the
+masks' resistance profile along x as a third input.
 """
 import argparse
 import json
@@ -40,6 +41,8 @@ def main(argv=None):
     ap.add_argument("--chunk", type=int, default=1024, help="samples per data-generation batch")
     ap.add_argument("--augment", action="store_true",
                     help="train on the data and its three mirror images (symmetries of the setup)")
+    ap.add_argument("--profile", action="store_true",
+                    help="third network input: the masks' resistance profile along x")
     ap.add_argument("--tta", action="store_true",
                     help="learned start: average the predictions of the mask's mirror images")
     ap.add_argument("--out", default=None)
@@ -52,8 +55,9 @@ def main(argv=None):
     torch.cuda.set_device(0)
     rep = {"args": vars(args)}
     t0 = time.perf_counter()
+    in_ch = 3 if args.profile else 2
     data = ws.generate(range(10000, 10000 + args.train), chunk=args.chunk,
-                       precision=args.precision, max_steps=args.max_steps, log=log)
+                       precision=args.precision, max_steps=args.max_steps, log=log, in_ch=in_ch)
     torch.cuda.synchronize()
     rep["data_seconds"] = time.perf_counter() - t0
     rep["train_samples_kept"] = len(data)
@@ -62,7 +66,7 @@ def main(argv=None):
     log(f"data: {len(data)} samples kept in {rep['data_seconds']:.1f} s, dropped {data.dropped}")
     scales = ws.scales_of(data)
     rep["u_scale"], rep["rho_scale"] = scales
-    net = ws.new_network(args.batch, seed=0)
+    net = ws.new_network(args.batch, seed=0, in_ch=in_ch)
     t0 = time.perf_counter()
     hist = ws.train(net, data, scales, epochs=args.epochs, lr=args.lr, lr_end=args.lr_end, log=log,
                     augment=args.augment)
@@ -108,7 +112,7 @@ def main(argv=None):
     if args.out:
         np.savez(args.out, params=net.params.cpu().numpy(), u_scale=np.array(scales[0]),
                  rho_scale=np.array(scales[1]),
-                 levels=np.array(4), base=np.array(32))
+                 levels=np.array(4), base=np.array(32), in_ch=np.array(in_ch))
     if args.report:
         with open(args.report, "w") as fh:
             json.dump(rep, fh, indent=1)

@@ -52,8 +52,25 @@ def sample(seed, nx=NX, ny=NY):
     return qsgs_2d(nx, ny, phi, seed), tau, phi
 
 
+PROFILE_SCALE = 10.0     # network input: resistance profile (wsn_column_profile) x 10
+
+
 def features(taus, nx):
     return np.array([lbm.knudsen(t, nx) / KN_SCALE for t in taus], np.float32)
+
+
+def inputs(solid, taus, in_ch=2, out=None):
+    """Network input of the masks solid (device uint8 [B,H,W]) and their taus:
+    mask and scaled Kn, and with in_ch = 3 the masks' resistance profile
+    along x (``wsn.column_profile``), which carries what lies upstream and
+    downstream of a pixel beyond the network's reach."""
+    feat = _dev(features(taus, solid.shape[2]))
+    if in_ch == 2:
+        return wsn.pack_input(solid, feat, out=out)
+    if in_ch != 3:
+        raise ValueError("in_ch must be 2 or 3")
+    return wsn.pack_input(solid, feat, out=out, profile=wsn.column_profile(solid),
+                          profile_scale=PROFILE_SCALE)
 
 
 def target_maps(taus, nx, scales, rho_in=RHO_IN, rho_out=RHO_OUT):
@@ -116,14 +133,15 @@ def solve(masks, taus, precision="fp32", tol=1e-9, max_steps=400000, starts=None
     return b, status, steps, resid, time.perf_counter() - t0
 
 
-def generate(seeds, chunk=1024, precision="fp32", tol=1e-9, max_steps=400000, log=None):
+def generate(seeds, chunk=1024, precision="fp32", tol=1e-9, max_steps=400000, log=None, in_ch=2):
     """Steady states of the samples `seeds` (zero-velocity start), in batches of
-    `chunk` samples.  Only samples that reach the residual are kept (packed in
-    seed order); the others are counted in `dropped`."""
+    `chunk` samples, with network inputs of in_ch channels (``inputs``).  Only
+    samples that reach the residual are kept (packed in seed order); the
+    others are counted in `dropped`."""
     import torch
     seeds = list(seeds)
     n = len(seeds)
-    x = torch.empty((n, NY, NX, 2), dtype=torch.float32, device="cuda")
+    x = torch.empty((n, NY, NX, in_ch), dtype=torch.float32, device="cuda")
     rho = torch.empty((n, NY, NX), dtype=torch.float32, device="cuda")
     u = torch.empty((n, 2, NY, NX), dtype=torch.float32, device="cuda")
     solid = torch.empty((n, NY, NX), dtype=torch.uint8, device="cuda")
@@ -158,7 +176,7 @@ def generate(seeds, chunk=1024, precision="fp32", tol=1e-9, max_steps=400000, lo
                 f"{len(part)} converged, steps median {int(np.median(st))} max {int(st.max())}, "
                 f"{sec:.1f} s")
     m = len(kept)
-    wsn.pack_input(solid[:m], _dev(features(taus, NX)), out=x[:m])
+    inputs(solid[:m], taus, in_ch, out=x[:m])
     d = Dataset(x[:m], rho[:m], u[:m], solid[:m], taus, steps, ks, np.ones(m, bool), kept)
     d.dropped = dropped
     return d
@@ -175,11 +193,12 @@ def scales_of(data, sample_count=64):
             float(np.sqrt((y[..., 0][fluid] ** 2).mean())))
 
 
-def new_network(batch, seed=0, levels=4, base=32):
-    """A U-Net with He-normal initial weights drawn from a seeded NumPy generator."""
+def new_network(batch, seed=0, levels=4, base=32, in_ch=2):
+    """A U-Net with He-normal initial weights drawn from a seeded NumPy generator
+    (in_ch input channels: 2, or 3 with the resistance profile)."""
     shapes = []
     ch = [base * 2 ** l for l in range(levels)]
-    cin = 2
+    cin = in_ch
     for l in range(levels):
         shapes += [(3, cin, ch[l]), (3, ch[l], ch[l])]
         cin = ch[l]
@@ -192,7 +211,7 @@ def new_network(batch, seed=0, levels=4, base=32):
         parts.append(rng.standard_normal(ks * ks * ci * co) * np.sqrt(2.0 / (ks * ks * ci)))
         parts.append(np.zeros(co))
     return wsn.WarmStartNet(np.concatenate(parts).astype(np.float32), batch, levels=levels,
-                            base=base, height=NY, width=NX)
+                            base=base, in_ch=in_ch, height=NY, width=NX)
 
 
 # Symmetries of the setup (Fig. 1) as (flip_h, flip_w) and the factors of the
@@ -209,13 +228,15 @@ MIRRORS = (((1, 0), (1.0, 1.0, -1.0)),
 
 def augmented(data, y):
     """Inputs, targets and masks of the data followed by those of its three
-    mirror images (MIRRORS): 4 n training samples from n solved ones."""
+    mirror images (MIRRORS): 4 n training samples from n solved ones.  The
+    inputs of a mirror image are formed from its mirrored masks."""
     import torch
     xs, ys, ss = [data.x], [y], [data.solid]
     for (fh, fw), sign in MIRRORS:
-        xs.append(wsn.mirror(data.x, fh, fw))
+        m = wsn.mirror(data.solid, fh, fw)
+        xs.append(inputs(m, data.taus, data.x.shape[3]))
         ys.append(wsn.mirror(y, fh, fw, sign))
-        ss.append(wsn.mirror(data.solid, fh, fw))
+        ss.append(m)
     return torch.cat(xs), torch.cat(ys), torch.cat(ss)
 
 
@@ -267,14 +288,14 @@ def predict(net, masks, taus, scales, tta=False):
         m = min(net.batch, n - c0)
         solid = _dev(np.stack(masks[c0:c0 + m]).astype(np.uint8))
         keep = _dev(np.stack([open_fluid(mk) for mk in masks[c0:c0 + m]]))
-        x = wsn.pack_input(solid, _dev(features(taus[c0:c0 + m], NX)))
-        y = net.infer(x)
+        tm = taus[c0:c0 + m]
+        y = net.infer(inputs(solid, tm, net.cfg.in_ch))
         if tta:
             w = 1.0 / (1 + len(MIRRORS))
             y = wsn.mirror(y, 0, 0, (w, w, w))
             for (fh, fw), sign in MIRRORS:
-                wsn.mirror(net.infer(wsn.mirror(x, fh, fw)), fh, fw, [w * v for v in sign],
-                           out=y, accumulate=True)
+                xv = inputs(wsn.mirror(solid, fh, fw), tm, net.cfg.in_ch)
+                wsn.mirror(net.infer(xv), fh, fw, [w * v for v in sign], out=y, accumulate=True)
         wsn.nhwc_to_fields(y, _dev(shift[c0:c0 + m]), _dev(inv[c0:c0 + m]),
                            slope=_dev(slope[c0:c0 + m]), keep_u=keep,
                            out=(rho[c0:c0 + m], u[c0:c0 + m], bad[c0:c0 + m]))

@@ -45,6 +45,8 @@ _SIGS = {
     "wsn_pack_input": (_c.c_int, [_p, _p, _i, _i, _i, _p, _p]),
     "wsn_fields_to_nhwc": (_c.c_int, [_p, _p, _p, _p, _p, _i, _i, _i, _p, _p]),
     "wsn_nhwc_to_fields": (_c.c_int, [_p, _p, _p, _p, _p, _i, _i, _i, _p, _p, _p, _p]),
+    "wsn_column_profile": (_c.c_int, [_p, _i, _i, _i, _p, _p]),
+    "wsn_pack_input_profile": (_c.c_int, [_p, _p, _p, _c.c_float, _i, _i, _i, _p, _p]),
     "wsn_mirror": (_c.c_int, [_p, _i, _i, _i, _i, _i, _i, _i, _c.POINTER(_c.c_float), _i, _p,
                               _p]),
 }
@@ -184,17 +186,39 @@ def adam(p, g, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):
                           float(lr), float(b1), float(b2), float(eps), int(t), _stream(p.device)))
 
 
-def pack_input(solid, feat, out=None):
-    """solid uint8 [B,H,W], feat float32 [B] -> x [B,H,W,2] (into `out` if given)."""
+def pack_input(solid, feat, out=None, profile=None, profile_scale=1.0):
+    """solid uint8 [B,H,W], feat float32 [B] -> x [B,H,W,2], or [B,H,W,3] with
+    profile float32 [B,W] (times profile_scale) as the third channel (into
+    `out` if given)."""
     import torch
     B, H, W = solid.shape
-    x = out if out is not None else torch.empty((B, H, W, 2), dtype=torch.float32,
+    C = 2 if profile is None else 3
+    x = out if out is not None else torch.empty((B, H, W, C), dtype=torch.float32,
                                                 device=solid.device)
-    if tuple(x.shape) != (B, H, W, 2):
+    if tuple(x.shape) != (B, H, W, C):
         raise ValueError("out has the wrong shape")
-    _check(lib().wsn_pack_input(_ptr(solid), _ptr(_f32(feat)), B, H, W, _ptr(x),
-                                _stream(solid.device)))
+    if profile is None:
+        _check(lib().wsn_pack_input(_ptr(solid), _ptr(_f32(feat)), B, H, W, _ptr(x),
+                                    _stream(solid.device)))
+    else:
+        if tuple(profile.shape) != (B, W):
+            raise ValueError("profile must be [B,W]")
+        _check(lib().wsn_pack_input_profile(_ptr(solid), _ptr(_f32(feat)), _ptr(_f32(profile)),
+                                            float(profile_scale), B, H, W, _ptr(x),
+                                            _stream(solid.device)))
     return x
+
+
+def column_profile(solid):
+    """solid uint8 [B,H,W] -> float32 [B,W]: the masks' resistance profiles
+    along x (wsn_column_profile)."""
+    import torch
+    if solid.dtype != torch.uint8 or not solid.is_contiguous() or not solid.is_cuda:
+        raise ValueError("expected a contiguous uint8 device tensor")
+    B, H, W = solid.shape
+    prof = torch.empty((B, W), dtype=torch.float32, device=solid.device)
+    _check(lib().wsn_column_profile(_ptr(solid), B, H, W, _ptr(prof), _stream(solid.device)))
+    return prof
 
 
 def fields_to_nhwc(rho, u, shift, scale, slope=None):

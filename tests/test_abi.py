@@ -238,6 +238,12 @@ def test_wsn_sizes_and_validation():
                  (None, 4, 1, 4, 4, 3, 1, 1, None, 0, other),
                  (fake, 4, 0, 4, 4, 3, 1, 1, None, 0, other)]:
         assert L.wsn_mirror(*args, None) == lbm.LBM_EINVAL, args
+    assert L.wsn_column_profile(None, 1, 4, 16, fake, None) == lbm.LBM_EINVAL
+    assert L.wsn_column_profile(fake, 0, 4, 16, fake, None) == lbm.LBM_EINVAL
+    assert L.wsn_column_profile(fake, 1, 4, 16385, fake, None) == lbm.LBM_EINVAL
+    assert L.wsn_pack_input_profile(fake, fake, None, 1.0, 1, 4, 16, fake, None) == lbm.LBM_EINVAL
+    assert L.wsn_pack_input_profile(fake, fake, fake, float("nan"), 1, 4, 16, fake,
+                                    None) == lbm.LBM_EINVAL
 
 
 def test_probe_rejects_bad_arguments():

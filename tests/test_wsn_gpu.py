@@ -41,6 +41,7 @@ def nl2(gpu, ref):
 CONV_CASES = [
     # B, H, W, cin, cout, ks
     (2, 8, 64, 2, 32, 3),       # first layer: 2 input channels
+    (2, 8, 64, 3, 32, 3),       # first layer with the resistance profile
     (1, 5, 16, 32, 32, 3),      # ragged tile rows (th = 4), narrow width
     (2, 6, 32, 64, 64, 3),      # th = 2 tiles
     (1, 4, 128, 96, 32, 3),     # decoder-level concatenation width
@@ -326,38 +327,77 @@ def test_mirror(fh, fw):
     assert np.array_equal(acc.cpu().numpy(), x + ref(x))
 
 
-def test_augmented_training_views():
+def _profile_ref(solid):
+    """The resistance profile of wsn_column_profile, in float64."""
+    B, H, W = solid.shape
+    phi = np.maximum((solid == 0).sum(axis=1) / H, 1.0 / H)
+    r = (1.0 - phi + 1.0 / H) ** 2 / phi ** 3
+    c = np.cumsum(r, axis=1) / r.sum(axis=1, keepdims=True)
+    return (np.arange(W) + 1.0) / (W + 1) - c
+
+
+@pytest.mark.parametrize("H,W", [(5, 37), (3, 300)])
+def test_column_profile_and_packing(H, W):
+    """The resistance profile against its formula (a fully solid column, a
+    fully fluid one, widths below and above one block), and the three-channel
+    input packing bitwise."""
+    B = 3
+    solid = (RNG.random((B, H, W)) < 0.4).astype(np.uint8)
+    solid[0, :, 2] = 1
+    solid[1, :, 5] = 0
+    ts = torch.tensor(solid, device="cuda")
+    prof = wsn.column_profile(ts).cpu().numpy()
+    assert np.abs(prof - _profile_ref(solid)).max() <= 2e-5   # FP32 running sum
+    feat = np.array([0.1, 0.5, 1.7], np.float32)
+    x = wsn.pack_input(ts, dev(feat), profile=dev(prof), profile_scale=10.0).cpu().numpy()
+    assert x.shape == (B, H, W, 3)
+    assert np.array_equal(x[..., 0], solid.astype(np.float32))
+    assert np.array_equal(x[..., 1], np.broadcast_to(feat[:, None, None], (B, H, W)))
+    assert np.array_equal(x[..., 2], np.broadcast_to((np.float32(10.0) * prof)[:, None, :],
+                                                     (B, H, W)))
+
+
+@pytest.mark.parametrize("in_ch", [2, 3])
+def test_augmented_training_views(in_ch):
     """The mirrored training data: the samples, then their three mirror images
-    with the target factors of MIRRORS (masks and inputs unscaled), bitwise
-    against NumPy's flips."""
+    with the target factors of MIRRORS, bitwise against NumPy's flips, and
+    inputs formed from the mirrored masks (the profile of an x-mirrored mask
+    is its own, not the mirrored profile)."""
     from paper_1609_09685_amd import warmstart as ws
     n, H, W = 3, 8, 16
-    x = RNG.standard_normal((n, H, W, 2)).astype(np.float32)
     y = RNG.standard_normal((n, H, W, 3)).astype(np.float32)
     solid = (RNG.random((n, H, W)) < 0.3).astype(np.uint8)
-    data = ws.Dataset(dev(x), None, None, torch.tensor(solid, device="cuda"), [0.6] * n,
-                      [0] * n, [0.0] * n, [True] * n, list(range(n)))
+    taus = [0.6, 0.7, 0.9]
+    ts = torch.tensor(solid, device="cuda")
+    x = ws.inputs(ts, taus, in_ch)
+    data = ws.Dataset(x, None, None, ts, taus, [0] * n, [0.0] * n, [True] * n, list(range(n)))
     xa, ya, sa = (t.cpu().numpy() for t in ws.augmented(data, dev(y)))
-    assert xa.shape == (4 * n, H, W, 2) and ya.shape == (4 * n, H, W, 3) and sa.shape == (4 * n, H, W)
+    assert xa.shape == (4 * n, H, W, in_ch) and ya.shape == (4 * n, H, W, 3)
+    assert sa.shape == (4 * n, H, W)
+    x = x.cpu().numpy()
     views = [((0, 0), (1.0, 1.0, 1.0))] + list(ws.MIRRORS)
     for v, ((fh, fw), sign) in enumerate(views):
         def flip(a):
             r = a[:, ::-1] if fh else a
             return r[:, :, ::-1] if fw else r
         blk = slice(v * n, (v + 1) * n)
-        assert np.array_equal(xa[blk], flip(x))
         assert np.array_equal(sa[blk], flip(solid))
+        assert np.array_equal(xa[blk][..., :2], flip(x)[..., :2])
         assert np.array_equal(ya[blk], flip(y) * np.asarray(sign, np.float32))
+        if in_ch == 3:
+            want = ws.PROFILE_SCALE * _profile_ref(flip(solid))
+            assert np.abs(xa[blk][..., 2] - want[:, None, :]).max() <= 2e-4
 
 
+@pytest.mark.parametrize("in_ch", [2, 3])
 @pytest.mark.parametrize("fh,fw", [(1, 0), (0, 1), (1, 1)])
-def test_averaged_prediction_is_mirror_equivariant(fh, fw):
+def test_averaged_prediction_is_mirror_equivariant(fh, fw, in_ch):
     """Averaged over the mirror images, the learned start of a mirrored mask is
     the mirrored start of the mask (density deviation from the linear drop and
     u_y with the factors of MIRRORS), for any weights: a flip or factor wrong
     anywhere in the averaging breaks it."""
     from paper_1609_09685_amd import warmstart as ws
-    net = ws.new_network(2, seed=3)
+    net = ws.new_network(2, seed=3, in_ch=in_ch)
     masks = [ws.sample(s)[0] for s in (20001, 20002)]
     taus = [0.6, 0.85]
     scales = (1.3, 0.2)
