@@ -43,6 +43,8 @@ def main(argv=None):
                     help="train on the data and its three mirror images (symmetries of the setup)")
     ap.add_argument("--profile", action="store_true",
                     help="third network input: the masks' resistance profile along x")
+    ap.add_argument("--rho-weight", type=float, default=1.0,
+                    help="weight of the density channel in the loss (its target scale / sqrt(w))")
     ap.add_argument("--tta", action="store_true",
                     help="learned start: average the predictions of the mask's mirror images")
     ap.add_argument("--out", default=None)
@@ -65,6 +67,9 @@ def main(argv=None):
     rep["train_steps_median"] = float(np.median(data.steps))
     log(f"data: {len(data)} samples kept in {rep['data_seconds']:.1f} s, dropped {data.dropped}")
     scales = ws.scales_of(data)
+    if args.rho_weight <= 0:
+        raise SystemExit("--rho-weight must be > 0")
+    scales = (scales[0], scales[1] / float(np.sqrt(args.rho_weight)))
     rep["u_scale"], rep["rho_scale"] = scales
     net = ws.new_network(args.batch, seed=0, in_ch=in_ch)
     t0 = time.perf_counter()
