@@ -41,6 +41,8 @@ def main(argv=None):
     ap.add_argument("--chunk", type=int, default=1024, help="samples per data-generation batch")
     ap.add_argument("--augment", action="store_true",
                     help="train on the data and its three mirror images (symmetries of the setup)")
+    ap.add_argument("--levels", type=int, default=4,
+                    help="U-Net levels (4: the configuration's network)")
     ap.add_argument("--profile", action="store_true",
                     help="third network input: the masks' resistance profile along x")
     ap.add_argument("--rho-weight", type=float, default=1.0,
@@ -71,7 +73,7 @@ def main(argv=None):
         raise SystemExit("--rho-weight must be > 0")
     scales = (scales[0], scales[1] / float(np.sqrt(args.rho_weight)))
     rep["u_scale"], rep["rho_scale"] = scales
-    net = ws.new_network(args.batch, seed=0, in_ch=in_ch)
+    net = ws.new_network(args.batch, seed=0, levels=args.levels, in_ch=in_ch)
     t0 = time.perf_counter()
     hist = ws.train(net, data, scales, epochs=args.epochs, lr=args.lr, lr_end=args.lr_end, log=log,
                     augment=args.augment)
@@ -117,7 +119,7 @@ def main(argv=None):
     if args.out:
         np.savez(args.out, params=net.params.cpu().numpy(), u_scale=np.array(scales[0]),
                  rho_scale=np.array(scales[1]),
-                 levels=np.array(4), base=np.array(32), in_ch=np.array(in_ch))
+                 levels=np.array(args.levels), base=np.array(32), in_ch=np.array(in_ch))
     if args.report:
         with open(args.report, "w") as fh:
             json.dump(rep, fh, indent=1)

@@ -49,6 +49,7 @@ CONV_CASES = [
     (1, 3, 48, 20, 40, 3),      # channels not multiples of the tiles
     (2, 4, 64, 32, 3, 1),       # 1x1 head
     (1, 2, 16, 256, 256, 3),    # bottom level
+    (1, 2, 32, 768, 256, 3),    # a fifth level's decoder input (512 + 256 channels)
 ]
 
 
